@@ -1,0 +1,54 @@
+"""Plant plausible mistakes in a copy of the oracle and check that the pins catch each one.
+
+Every mutant is a one-token change of ``oracle/evosort_oracle.c`` (a flipped
+tie rule, a wrong mask, a dropped complement, a shifted digit, an off-by-one in
+a count), compiled into a temporary directory.  The pin suite is re-run against
+it in a child process; the test passes only if that run fails.  The real oracle
+is never modified.  Mutants are chosen so that none can write out of bounds.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "evosort_oracle.c")
+
+MUTANTS = {
+    "mergesort tie takes the right run": (
+        "        if (r[b].u < r[a].u)\n            tmp[k++] = r[b++];",
+        "        if (r[b].u <= r[a].u)\n            tmp[k++] = r[b++];"),
+    "int32 offset off by one": ("(int64_t)v + 2147483648LL", "(int64_t)v + 2147483647LL"),
+    "int64 offset wrong bit": ("return (uint64_t)v + (UINT64_C(1) << 63);", "return (uint64_t)v + (UINT64_C(1) << 62);"),
+    "float32 negative not complemented": ("return (uint64_t)(uint32_t)~b;", "return (uint64_t)b;"),
+    "float64 positive sign bit not set": ("return b | (UINT64_C(1) << 63);", "return b;"),
+    "counting pass reads the wrong digit": (
+        "        next[(u >> shift) & (bins - 1)] += 1;", "        next[(u >> (shift + 1)) & (bins - 1)] += 1;"),
+    "histogram drops the pass index": ("hist[(uint64_t)p * bins + d] += 1;", "hist[d] += 0 * p + 1;"),
+    "insertion sort unstable": ("while (j >= lo && r[j].u > x.u)", "while (j >= lo && r[j].u >= x.u)"),
+    "merge round tie takes the right run": (
+        "            if (r[b].u < r[a].u)\n                perm_out[k++] = r[b++].idx;",
+        "            if (r[b].u <= r[a].u)\n                perm_out[k++] = r[b++].idx;"),
+    "rank counts the element itself": ("(uk == ui && k < i)", "(uk == ui && k <= i)"),
+    "unsorted check compares the wrong way": (
+        "order_key(kind, base, j) > order_key(kind, base, j + 1)",
+        "order_key(kind, base, j) < order_key(kind, base, j + 1)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    before, after = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(before) == 1, f"mutation site not unique or missing: {name}"
+    mutant_c = tmp_path / "mutant.c"
+    mutant_c.write_text(src.replace(before, after))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", str(mutant_c), "-o", str(lib)], check=True)
+    env = dict(os.environ, EVOSORT_TEST_ORACLE_MUTANT=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"pins did not catch mutant {name!r}:\n{r.stdout[-2000:]}"
+    assert "failed" in r.stdout or "Error" in r.stdout
