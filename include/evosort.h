@@ -1,0 +1,280 @@
+/*
+ * evosort.h -- C ABI of the EvoSort GPU sort library for AMD MI355X (gfx950).
+ *
+ * The library sorts one array of fixed-width keys on one GPU, ascending and
+ * stably, optionally carrying one value per key, or returns the sorting
+ * permutation.  It follows the paper's drop-in statement of the problem
+ * (Sec. 1 and the opening of Sec. 4): one call takes an array and hands it
+ * back sorted, usable wherever a library sort is; here the result is the one
+ * a stable library sort gives.
+ *
+ * Two routines do the work and the adaptive partition sort chooses between
+ * them (Sec. 4.3, Algorithm 6):
+ *   - a block-based LSD radix sort (Sec. 4, Algorithms 4 and 5), built as an
+ *     all-pass digit histogram, one device-wide scan of the digit counts and
+ *     one single-sweep pass per digit with a decoupled look-back chained scan;
+ *   - a bottom-up mergesort (Sec. 4, Algorithm 3): chunks of T_ins keys are
+ *     sorted, then runs are merged pairwise with doubling length;
+ *   - below a fallback threshold (the paper's T_numpy) one workgroup sorts the
+ *     whole array (the paper hands such arrays to the platform's library sort).
+ * The tunables of the paper's parameter vector (Sec. 3.2 and Sec. 4.2:
+ * T_insertion, A_code, T_numpy) are fields of evosort_params, together with
+ * the GPU's own knobs (digit width, tile shape).
+ *
+ * Key order.  Integer keys order by value.  Float keys order by IEEE-754
+ * totalOrder: -NaN < -inf < ... < -0.0 < +0.0 < ... < +inf < +NaN.  Equal
+ * keys keep their input order, so every routine and every parameter setting
+ * gives the same bytes.
+ *
+ * Conventions for every call below:
+ *   - Pointers named keys_*, vals_*, idx_*, temp, hist_*, bases_* are DEVICE
+ *     pointers (hipMalloc'd or equivalent) on the current HIP device; sizes
+ *     are element counts unless named *_bytes.  The caller owns all memory;
+ *     the library never allocates device memory on a sort call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it and the call returns before the work ends; read
+ *     the outputs after synchronizing that stream.
+ *   - Argument errors are returned synchronously and nothing is enqueued.
+ *     A failed HIP launch returns EVOSORT_ERR_HIP; evosort_last_hip_error()
+ *     then gives the hipError_t of that failure (per host thread).
+ *   - `temp` is scratch device memory of at least the size
+ *     evosort_temp_bytes() reports for the same arguments; 256-byte alignment
+ *     is required.  Its contents on entry do not matter.  Calls that share a
+ *     temp buffer must not overlap in time.
+ *   - In-place operation is allowed where stated (keys_out == keys_in,
+ *     vals_out == vals_in).  Any other overlap between distinct input,
+ *     output and temp buffers returns EVOSORT_ERR_INVALID_ARG.
+ *   - All functions are safe to call from several host threads as long as
+ *     their buffers are distinct.
+ */
+#ifndef EVOSORT_H_
+#define EVOSORT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Key types. */
+typedef enum evosort_dtype {
+    EVOSORT_INT32 = 1,
+    EVOSORT_INT64 = 2,
+    EVOSORT_UINT32 = 3,
+    EVOSORT_FLOAT32 = 4,
+    EVOSORT_FLOAT64 = 5
+} evosort_dtype;
+
+/* Routine choice: the paper's A_code (Sec. 4.2): 3 = mergesort, 4 = LSD radix
+ * sort.  0 = automatic (radix, the routine the paper's tuner picked at every
+ * size, Sec. 6).  Other values are rejected with EVOSORT_ERR_INVALID_ARG. */
+typedef enum evosort_algo {
+    EVOSORT_ALGO_AUTO = 0,
+    EVOSORT_ALGO_MERGE = 3,
+    EVOSORT_ALGO_RADIX = 4
+} evosort_algo;
+
+typedef enum evosort_status {
+    EVOSORT_OK = 0,
+    EVOSORT_ERR_INVALID_ARG = 1,       /* null pointer with n > 0, n < 0, bad overlap, bad param */
+    EVOSORT_ERR_UNSUPPORTED_DTYPE = 2, /* dtype or value/index width not supported */
+    EVOSORT_ERR_UNSUPPORTED_PARAM = 3, /* e.g. a tile shape that is not compiled in */
+    EVOSORT_ERR_TEMP_TOO_SMALL = 4,    /* temp_bytes below evosort_temp_bytes() */
+    EVOSORT_ERR_HIP = 5,               /* a HIP launch or runtime call failed */
+    EVOSORT_ERR_DEVICE_TIMEOUT = 6     /* a kernel's bounded wait ran out (see evosort_check_device_error) */
+} evosort_status;
+
+/* Operations, for evosort_temp_bytes and evosort_plan. */
+typedef enum evosort_op {
+    EVOSORT_OP_SORT = 0,       /* keys only */
+    EVOSORT_OP_SORT_PAIRS = 1, /* keys and values of value_bytes each */
+    EVOSORT_OP_ARGSORT = 2     /* keys in, permutation out, index of value_bytes (4 or 8) */
+} evosort_op;
+
+/* Routine a call takes (the branches of Sec. 4.3, Algorithm 6). */
+typedef enum evosort_path {
+    EVOSORT_PATH_COPY = 0,  /* n <= 1: at most a copy */
+    EVOSORT_PATH_SMALL = 1, /* n below the fallback threshold: one workgroup sorts all */
+    EVOSORT_PATH_RADIX = 2, /* block-based LSD radix sort */
+    EVOSORT_PATH_MERGE = 3  /* bottom-up mergesort */
+} evosort_path;
+
+/* Debug switches (evosort_params.debug_flags).  Test use only. */
+#define EVOSORT_DEBUG_WITHHOLD_TILE0 0x1u /* radix tile 0 never publishes its counts: later
+                                            tiles run out of spin_limit and the call reports
+                                            EVOSORT_ERR_DEVICE_TIMEOUT through the error word */
+
+/*
+ * Parameters.  Always initialise with evosort_default_params() and then change
+ * fields; struct_size guards the ABI.
+ *
+ *   algo                 A_code: EVOSORT_ALGO_AUTO, _MERGE or _RADIX.
+ *   digit_bits           radix digit width d, 4..12; the paper fixes 8 (Sec. 4,
+ *                        Algorithms 4 and 5).  ceil(8*key_bytes/d) passes.
+ *   insertion_threshold  T_ins, 1..2048 (the paper's bounds are [2, 2048],
+ *                        Sec. 4.2): length of the chunks the mergesort sorts
+ *                        before its first merge (Sec. 4, Algorithm 3).
+ *   fallback_threshold   T_numpy: arrays with n < this go to the one-workgroup
+ *                        sort.  Capped by what one workgroup holds
+ *                        (evosort_plan reports the cap as small_capacity).
+ *   block_threads,       GPU tile shape of the radix passes (threads per
+ *   items_per_thread     workgroup, keys per thread); 0 = library default.
+ *                        Only compiled-in shapes are accepted.
+ *   spin_limit           bound on the look-back wait of a radix tile, in
+ *                        polls; 0 = library default.  When it runs out the
+ *                        kernel records EVOSORT_ERR_DEVICE_TIMEOUT in temp and
+ *                        finishes (the output is then undefined).
+ *   debug_flags          EVOSORT_DEBUG_* bits; 0 in normal use.
+ */
+typedef struct evosort_params {
+    uint32_t struct_size;
+    int32_t algo;
+    uint32_t digit_bits;
+    uint32_t insertion_threshold;
+    uint64_t fallback_threshold;
+    uint32_t block_threads;
+    uint32_t items_per_thread;
+    uint32_t spin_limit;
+    uint32_t debug_flags;
+} evosort_params;
+
+/* What a call with the given arguments would do (host only; no GPU needed). */
+typedef struct evosort_plan_info {
+    int32_t path;             /* evosort_path */
+    uint32_t passes;          /* radix passes (0 unless path == RADIX) */
+    uint32_t digit_bits;      /* effective d */
+    uint32_t block_threads;   /* radix tile shape in effect */
+    uint32_t items_per_thread;
+    uint32_t status_bytes;    /* width of a look-back status word: 4 (n < 2^30) or 8 */
+    uint64_t tile_keys;       /* keys per radix tile, or per mergesort block */
+    uint64_t tiles;           /* radix tiles per pass, or mergesort blocks */
+    uint32_t merge_rounds;    /* global merge rounds after the block sort (path == MERGE) */
+    uint32_t reserved;
+    uint64_t merge_block_run; /* sorted run length after the mergesort block sort */
+    uint64_t small_capacity;  /* largest n the one-workgroup sort takes for this dtype/op */
+    uint64_t temp_bytes;      /* same as evosort_temp_bytes */
+} evosort_plan_info;
+
+/* Fill *p with the defaults (struct_size set; algo AUTO; d = 8; T_ins = 8;
+ * fallback = the one-workgroup capacity; default tile shape). */
+void evosort_default_params(evosort_params *p);
+
+/* Scratch size for an operation.  value_bytes: 0 for EVOSORT_OP_SORT, 4 or 8
+ * otherwise (for ARGSORT it is the index width).  p may be NULL (defaults). */
+evosort_status evosort_temp_bytes(int op, int dtype, int64_t n, uint32_t value_bytes,
+                                  const evosort_params *p, size_t *out_bytes);
+
+/* The routine and launch shape a call would use; host only. */
+evosort_status evosort_plan(int op, int dtype, int64_t n, uint32_t value_bytes,
+                            const evosort_params *p, evosort_plan_info *out);
+
+/*
+ * Sort keys (Sec. 4.3, Algorithm 6, and the routines it calls).
+ * keys_in: n keys of `dtype`, read only unless keys_out == keys_in (in place).
+ * keys_out: n keys, written with keys_in in ascending order (original bits).
+ */
+evosort_status evosort_sort(int dtype, const void *keys_in, void *keys_out, int64_t n, void *temp,
+                            size_t temp_bytes, const evosort_params *p, void *stream);
+
+/*
+ * Sort key-value pairs stably by key.  Values are opaque value_bytes-wide
+ * words (4 or 8) that travel with their keys; equal keys keep input order.
+ * In place is allowed for keys and for values.
+ */
+evosort_status evosort_sort_pairs(int dtype, const void *keys_in, void *keys_out, const void *vals_in,
+                                  void *vals_out, uint32_t value_bytes, int64_t n, void *temp,
+                                  size_t temp_bytes, const evosort_params *p, void *stream);
+
+/*
+ * Stable sorting permutation: idx_out[j] = input position of the key that a
+ * stable sort places at j.  index_bytes 4 (int32, needs n <= 2^31 - 1) or 8
+ * (int64).  keys_in is never written.
+ */
+evosort_status evosort_argsort(int dtype, const void *keys_in, void *idx_out, uint32_t index_bytes, int64_t n,
+                               void *temp, size_t temp_bytes, const evosort_params *p, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Single steps of the two routines, exported so each can be checked alone.  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Radix steps 1-2: digit histograms of all passes and their exclusive prefix
+ * sums (Sec. 4, Algorithm 4: per-thread counts combined into one histogram
+ * per pass, then prefix sums; here one read of the keys serves every pass).
+ * hist_out and bases_out: device arrays of passes * 2^digit_bits uint64,
+ * row p = pass p (digit bits [p*d, p*d + d) of the order key).  bases_out may
+ * be NULL.  temp as for evosort_sort with the same dtype and n.
+ */
+evosort_status evosort_radix_histogram(int dtype, const void *keys, int64_t n, uint32_t digit_bits,
+                                       uint64_t *hist_out, uint64_t *bases_out, void *temp, size_t temp_bytes,
+                                       void *stream);
+
+/*
+ * Radix step 3: one stable LSD pass on digit `pass` (Sec. 4, Algorithm 4,
+ * loop body: offsets, then placement into the other buffer).  Equivalent to a
+ * stable counting sort of the input on that digit.  vals may be NULL
+ * (value_bytes 0).  Not in place.  temp as for evosort_sort_pairs (or
+ * evosort_sort when keys only) with the same arguments.
+ */
+evosort_status evosort_radix_pass(int dtype, const void *keys_in, void *keys_out, const void *vals_in,
+                                  void *vals_out, uint32_t value_bytes, int64_t n, uint32_t pass,
+                                  void *temp, size_t temp_bytes, const evosort_params *p, void *stream);
+
+/*
+ * Mergesort step 1: sort every block of the mergesort on its own: each block
+ * of evosort_plan().merge_block_run keys is cut into chunks of T_ins keys,
+ * each chunk is sorted, then the chunks are merged pairwise inside the block
+ * (Sec. 4, Algorithm 3, first loop and the first merge rounds).  Not in place.
+ * *run_out receives the run length produced.
+ */
+evosort_status evosort_merge_block_sort(int dtype, const void *keys_in, void *keys_out, const void *vals_in,
+                                        void *vals_out, uint32_t value_bytes, int64_t n, const evosort_params *p,
+                                        int64_t *run_out, void *stream);
+
+/*
+ * Mergesort step 2: one merge round (Sec. 4, Algorithm 3, while-loop body):
+ * runs [2k*run, (2k+1)*run) and [(2k+1)*run, (2k+2)*run) of keys_in, each
+ * sorted, are merged into keys_out (ties take the left run; a trailing run
+ * without a partner is copied).  Not in place.  temp: the merge-path split
+ * points of this round; 256 + 8 * (n + 4) bytes always suffice
+ * (EVOSORT_ERR_TEMP_TOO_SMALL otherwise).
+ */
+evosort_status evosort_merge_round(int dtype, const void *keys_in, void *keys_out, const void *vals_in,
+                                   void *vals_out, uint32_t value_bytes, int64_t n, int64_t run, void *temp,
+                                   size_t temp_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Errors and measurement.                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Static text for a status code. */
+const char *evosort_status_string(int status);
+
+/* hipError_t behind the last EVOSORT_ERR_HIP on this host thread (0 if none). */
+int evosort_last_hip_error(void);
+
+/*
+ * Synchronize `stream` and read the device error word a radix call left in
+ * `temp`: EVOSORT_OK, or EVOSORT_ERR_DEVICE_TIMEOUT if a look-back wait ran
+ * out of spin_limit.  temp/temp_bytes as passed to that call.
+ */
+evosort_status evosort_check_device_error(const void *temp, size_t temp_bytes, void *stream);
+
+/*
+ * Kernel timing with HIP events.  While enabled, every kernel launch of the
+ * library is bracketed by two events recorded on the launch stream.
+ * evosort_profile_collect synchronizes those events and folds them into
+ * per-kernel totals; evosort_profile_get reads kernel i (0 <= i < count).
+ * Off by default; costs two event records per launch when on.
+ */
+void evosort_profile_enable(int on);
+void evosort_profile_reset(void);
+int evosort_profile_collect(void);
+evosort_status evosort_profile_get(int i, char *name, size_t name_len, uint64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EVOSORT_H_ */

@@ -13,13 +13,13 @@ stable sort (see the C file's header):
 * :func:`sort`, :func:`sort_pairs`, :func:`argsort` -- results of the three
   library calls, obtained by gathering through that permutation;
 * :func:`digit_histogram`, :func:`digit_bases`, :func:`counting_pass` -- the
-  steps of one LSD radix pass (Sec. 4.3, the block-based LSD radix sort);
+  steps of one LSD radix pass (Sec. 4, Algorithms 4 and 5, the block-based LSD radix sort);
 * :func:`insertion_chunks`, :func:`merge_round` -- the steps of the bottom-up
-  mergesort (Sec. 4.3, the refined parallel mergesort);
+  mergesort (Sec. 4, Algorithm 3, the refined parallel mergesort);
 * :func:`rank_of`, :func:`first_unsorted` -- sampled and property checks for
   sizes the full host sort is too slow for;
 * :func:`aps_path` -- which routine the adaptive partition sort picks
-  (Sec. 4.4, Alg. "AdaptivePartitionSort").
+  (Sec. 4.3, Algorithm 6, AdaptivePartitionSort).
 """
 from __future__ import annotations
 
@@ -196,7 +196,7 @@ def first_unsorted(keys: np.ndarray) -> int:
     return int(_load().oracle_first_unsorted(_kind(keys), _ptr(keys), keys.size))
 
 
-# Routine codes of the adaptive partition sort (Sec. 3.2 / 4.4: A_code 3 is the
+# Routine codes of the adaptive partition sort (Sec. 4.2: A_code 3 is the
 # mergesort, A_code 4 the LSD radix sort).
 A_MERGE = 3
 A_RADIX = 4
@@ -204,19 +204,20 @@ A_RADIX = 4
 
 def aps_path(n: int, integer_keys: bool, a_code: int, t_fallback: int, small_capacity: int,
              radix_for_floats: bool = True) -> str:
-    """Routine chosen by the adaptive partition sort (Sec. 4.4, Alg. "AdaptivePartitionSort").
+    """Routine chosen by the adaptive partition sort (Sec. 4.3, Algorithm 6, AdaptivePartitionSort).
 
     The paper's rule: below the library-sort threshold use the small-array
     sort; else the LSD radix sort when A_code is 4 and the keys are integers;
     else the refined mergesort (A_code 3, and every other code, in the paper).
 
     Readings for the GPU library: the small-array sort is one workgroup, so the
-    threshold is capped at what one workgroup holds (``small_capacity``); float
+    branch also needs n to fit in one workgroup (``small_capacity`` is the
+    largest n it takes); float
     keys take the radix branch too when ``radix_for_floats`` (their keys are
     mapped to unsigned integers); A_code 0 means "automatic" and picks the radix
     sort, which the paper's tuner chose at every size.
     """
-    if n < min(t_fallback, small_capacity):
+    if n < t_fallback and n <= small_capacity:
         return "small"
     if a_code in (0, A_RADIX) and (integer_keys or radix_for_floats):
         return "radix"

@@ -22,12 +22,12 @@
  * paper's description, so that the GPU steps can be checked one at a time:
  *
  *   - oracle_digit_histogram : per-digit counts of every radix pass
- *                              (Sec. 4.3, Alg. "RefinedParallelRadixSort_int32",
+ *                              (Sec. 4, Algorithm 4, RefinedParallelRadixSort_int32,
  *                              histogram step; 8-bit digits there, width free here)
  *   - oracle_counting_pass   : one stable LSD pass on one digit (same algorithm,
  *                              prefix-sum + scatter step)
  *   - oracle_insertion_chunks: insertion sort of every chunk of a given length
- *                              (Sec. 4.3, Alg. "RefinedParallelMergeSort", first loop)
+ *                              (Sec. 4, Algorithm 3, RefinedParallelMergeSort, first loop)
  *   - oracle_merge_round     : one merge round over pairs of adjacent sorted runs
  *                              (same algorithm, while-loop body)
  *   - oracle_rank_of         : the output position of one input element under
@@ -78,7 +78,7 @@ static int kind_bytes(int kind)
  *
  *  - signed integers: offset binary, u = v - INT_MIN, computed as an integer
  *    addition (the paper flips the sign bit with XOR 0x80000000 and
- *    0x8000000000000000, Sec. 4.3; for two's complement this is the same map);
+ *    0x8000000000000000, Sec. 4, Algorithms 4 and 5; for two's complement this is the same map);
  *  - unsigned 32-bit: u = v;
  *  - IEEE floats: a value with the sign bit set is negative (or -0.0 or a
  *    negative-signed NaN): larger magnitude must give a smaller key, so the

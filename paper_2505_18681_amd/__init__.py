@@ -1,0 +1,373 @@
+"""EvoSort on AMD MI355X: Python binding of ``libevosort.so``.
+
+This module only marshals arguments: it checks tensors, allocates the output
+and scratch tensors with PyTorch on the keys' device, and calls the C ABI
+declared in ``include/evosort.h`` on PyTorch's current stream.  Every step of
+every sort runs in the library's HIP kernels; there is no CPU path.  Importing
+the package fails if the library has not been built
+(``python -m paper_2505_18681_amd.build``).
+
+Public calls (names follow the C ABI):
+
+* :func:`sort`, :func:`sort_pairs`, :func:`argsort` -- the three library sorts;
+* :func:`radix_histogram`, :func:`radix_pass`, :func:`merge_block_sort`,
+  :func:`merge_round` -- single steps of the two routines;
+* :func:`plan`, :func:`temp_bytes`, :func:`default_params` -- host-only queries;
+* :func:`profile_enable`, :func:`profile_reset`, :func:`profile_collect` --
+  per-kernel HIP-event timing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libevosort.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2505_18681_amd.build` first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---------------------------------------------------------------- constants --
+INT32, INT64, UINT32, FLOAT32, FLOAT64 = 1, 2, 3, 4, 5
+ALGO_AUTO, ALGO_MERGE, ALGO_RADIX = 0, 3, 4
+OP_SORT, OP_SORT_PAIRS, OP_ARGSORT = 0, 1, 2
+PATH_NAMES = {0: "copy", 1: "small", 2: "radix", 3: "merge"}
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED_DTYPE, ERR_UNSUPPORTED_PARAM, ERR_TEMP_TOO_SMALL, ERR_HIP, ERR_DEVICE_TIMEOUT = \
+    range(7)
+DEBUG_WITHHOLD_TILE0 = 0x1
+
+EXPORTED = (
+    "evosort_default_params", "evosort_temp_bytes", "evosort_plan", "evosort_sort", "evosort_sort_pairs",
+    "evosort_argsort", "evosort_radix_histogram", "evosort_radix_pass", "evosort_merge_block_sort",
+    "evosort_merge_round", "evosort_status_string", "evosort_last_hip_error", "evosort_check_device_error",
+    "evosort_profile_enable", "evosort_profile_reset", "evosort_profile_collect", "evosort_profile_get",
+)
+
+
+class Params(ctypes.Structure):
+    """``evosort_params`` (see include/evosort.h)."""
+
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("algo", ctypes.c_int32),
+        ("digit_bits", ctypes.c_uint32),
+        ("insertion_threshold", ctypes.c_uint32),
+        ("fallback_threshold", ctypes.c_uint64),
+        ("block_threads", ctypes.c_uint32),
+        ("items_per_thread", ctypes.c_uint32),
+        ("spin_limit", ctypes.c_uint32),
+        ("debug_flags", ctypes.c_uint32),
+    ]
+
+    def __repr__(self):
+        return "Params(" + ", ".join(f"{n}={getattr(self, n)}" for n, _ in self._fields_[1:]) + ")"
+
+
+class PlanInfo(ctypes.Structure):
+    """``evosort_plan_info`` (see include/evosort.h)."""
+
+    _fields_ = [
+        ("path", ctypes.c_int32),
+        ("passes", ctypes.c_uint32),
+        ("digit_bits", ctypes.c_uint32),
+        ("block_threads", ctypes.c_uint32),
+        ("items_per_thread", ctypes.c_uint32),
+        ("status_bytes", ctypes.c_uint32),
+        ("tile_keys", ctypes.c_uint64),
+        ("tiles", ctypes.c_uint64),
+        ("merge_rounds", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("merge_block_run", ctypes.c_uint64),
+        ("small_capacity", ctypes.c_uint64),
+        ("temp_bytes", ctypes.c_uint64),
+    ]
+
+
+_vp, _i64, _u32, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int, ctypes.c_size_t
+_P = ctypes.POINTER(Params)
+
+_lib.evosort_default_params.argtypes = [_P]
+_lib.evosort_default_params.restype = None
+_lib.evosort_temp_bytes.argtypes = [_i32, _i32, _i64, _u32, _P, ctypes.POINTER(_sz)]
+_lib.evosort_plan.argtypes = [_i32, _i32, _i64, _u32, _P, ctypes.POINTER(PlanInfo)]
+_lib.evosort_sort.argtypes = [_i32, _vp, _vp, _i64, _vp, _sz, _P, _vp]
+_lib.evosort_sort_pairs.argtypes = [_i32, _vp, _vp, _vp, _vp, _u32, _i64, _vp, _sz, _P, _vp]
+_lib.evosort_argsort.argtypes = [_i32, _vp, _vp, _u32, _i64, _vp, _sz, _P, _vp]
+_lib.evosort_radix_histogram.argtypes = [_i32, _vp, _i64, _u32, _vp, _vp, _vp, _sz, _vp]
+_lib.evosort_radix_pass.argtypes = [_i32, _vp, _vp, _vp, _vp, _u32, _i64, _u32, _vp, _sz, _P, _vp]
+_lib.evosort_merge_block_sort.argtypes = [_i32, _vp, _vp, _vp, _vp, _u32, _i64, _P, ctypes.POINTER(_i64), _vp]
+_lib.evosort_merge_round.argtypes = [_i32, _vp, _vp, _vp, _vp, _u32, _i64, _i64, _vp, _sz, _vp]
+_lib.evosort_status_string.argtypes = [_i32]
+_lib.evosort_status_string.restype = ctypes.c_char_p
+_lib.evosort_last_hip_error.argtypes = []
+_lib.evosort_check_device_error.argtypes = [_vp, _sz, _vp]
+_lib.evosort_profile_enable.argtypes = [_i32]
+_lib.evosort_profile_enable.restype = None
+_lib.evosort_profile_reset.argtypes = []
+_lib.evosort_profile_reset.restype = None
+_lib.evosort_profile_collect.argtypes = []
+_lib.evosort_profile_get.argtypes = [_i32, ctypes.c_char_p, _sz, ctypes.POINTER(ctypes.c_uint64),
+                                     ctypes.POINTER(ctypes.c_double)]
+for _f in ("evosort_temp_bytes", "evosort_plan", "evosort_sort", "evosort_sort_pairs", "evosort_argsort",
+           "evosort_radix_histogram", "evosort_radix_pass", "evosort_merge_block_sort", "evosort_merge_round",
+           "evosort_last_hip_error", "evosort_check_device_error", "evosort_profile_collect", "evosort_profile_get"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+class EvosortError(RuntimeError):
+    def __init__(self, where: str, status: int):
+        self.status = status
+        msg = status_string(status)
+        if status == ERR_HIP:
+            msg += f" (hipError_t {_lib.evosort_last_hip_error()})"
+        super().__init__(f"{where}: {msg}")
+
+
+def status_string(status: int) -> str:
+    return _lib.evosort_status_string(int(status)).decode()
+
+
+def _check(where: str, st: int):
+    if st != OK:
+        raise EvosortError(where, st)
+
+
+# ------------------------------------------------------------- host queries --
+def default_params(**overrides) -> Params:
+    """``evosort_default_params`` with keyword overrides (e.g. ``algo=ALGO_MERGE``)."""
+    p = Params()
+    _lib.evosort_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k) or k == "struct_size":
+            raise AttributeError(f"no parameter {k!r}")
+        setattr(p, k, v)
+    return p
+
+
+def _pp(params):
+    return ctypes.byref(params) if params is not None else None
+
+
+def temp_bytes(op: int, dtype_code: int, n: int, value_bytes: int = 0, params: Params | None = None) -> int:
+    out = _sz(0)
+    _check("evosort_temp_bytes", _lib.evosort_temp_bytes(op, dtype_code, n, value_bytes, _pp(params),
+                                                         ctypes.byref(out)))
+    return int(out.value)
+
+
+def plan(op: int, dtype_code: int, n: int, value_bytes: int = 0, params: Params | None = None) -> dict:
+    info = PlanInfo()
+    _check("evosort_plan", _lib.evosort_plan(op, dtype_code, n, value_bytes, _pp(params), ctypes.byref(info)))
+    d = {name: getattr(info, name) for name, _ in PlanInfo._fields_ if name != "reserved"}
+    d["path_name"] = PATH_NAMES.get(info.path, "?")
+    return d
+
+
+# ------------------------------------------------------------ tensor helpers --
+def _torch():
+    import torch
+
+    return torch
+
+
+def dtype_code(dtype) -> int:
+    torch = _torch()
+    table = {torch.int32: INT32, torch.int64: INT64, torch.float32: FLOAT32, torch.float64: FLOAT64}
+    if hasattr(torch, "uint32"):
+        table[torch.uint32] = UINT32
+    if dtype not in table:
+        raise TypeError(f"evosort: unsupported key dtype {dtype}")
+    return table[dtype]
+
+
+def _key_tensor(t, what="keys"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{what} must be on a GPU device (got {t.device}); the library has no CPU path")
+    if t.dim() != 1 or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous 1-D tensor")
+    return t
+
+
+def _stream(device, stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _temp(nbytes: int, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
+
+
+# ---------------------------------------------------------------- the sorts --
+def sort(keys, *, params: Params | None = None, out=None, stream=None, temp=None):
+    """Keys in ascending order (stable; floats in IEEE totalOrder).  ``out=keys`` sorts in place."""
+    torch = _torch()
+    keys = _key_tensor(keys)
+    code = dtype_code(keys.dtype)
+    n = keys.numel()
+    if out is None:
+        out = torch.empty_like(keys)
+    _key_tensor(out, "out")
+    if out.dtype != keys.dtype or out.numel() != n:
+        raise ValueError("out must match keys in dtype and length")
+    need = temp_bytes(OP_SORT, code, n, 0, params)
+    tmp = temp if temp is not None else _temp(need, keys.device)
+    with torch.cuda.device(keys.device):
+        _check("evosort_sort", _lib.evosort_sort(code, _ptr(keys), _ptr(out), n, _ptr(tmp), tmp.numel(),
+                                                 _pp(params), _stream(keys.device, stream)))
+    return out
+
+
+def sort_pairs(keys, values, *, params: Params | None = None, keys_out=None, values_out=None, stream=None,
+               temp=None):
+    """(keys, values) sorted stably by key; values are opaque 4- or 8-byte words."""
+    torch = _torch()
+    keys = _key_tensor(keys)
+    values = _key_tensor(values, "values")
+    code = dtype_code(keys.dtype)
+    n = keys.numel()
+    if values.numel() != n:
+        raise ValueError("keys and values differ in length")
+    vb = values.element_size()
+    if vb not in (4, 8):
+        raise TypeError("values must be 4- or 8-byte elements")
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    values_out = torch.empty_like(values) if values_out is None else values_out
+    need = temp_bytes(OP_SORT_PAIRS, code, n, vb, params)
+    tmp = temp if temp is not None else _temp(need, keys.device)
+    with torch.cuda.device(keys.device):
+        _check("evosort_sort_pairs",
+               _lib.evosort_sort_pairs(code, _ptr(keys), _ptr(keys_out), _ptr(values), _ptr(values_out), vb, n,
+                                       _ptr(tmp), tmp.numel(), _pp(params), _stream(keys.device, stream)))
+    return keys_out, values_out
+
+
+def argsort(keys, *, index_dtype=None, params: Params | None = None, out=None, stream=None, temp=None):
+    """Stable sorting permutation (int64 by default, or int32)."""
+    torch = _torch()
+    keys = _key_tensor(keys)
+    code = dtype_code(keys.dtype)
+    n = keys.numel()
+    index_dtype = index_dtype or torch.int64
+    if index_dtype not in (torch.int32, torch.int64):
+        raise TypeError("index_dtype must be torch.int32 or torch.int64")
+    ib = 4 if index_dtype == torch.int32 else 8
+    out = torch.empty(n, dtype=index_dtype, device=keys.device) if out is None else out
+    need = temp_bytes(OP_ARGSORT, code, n, ib, params)
+    tmp = temp if temp is not None else _temp(need, keys.device)
+    with torch.cuda.device(keys.device):
+        _check("evosort_argsort", _lib.evosort_argsort(code, _ptr(keys), _ptr(out), ib, n, _ptr(tmp), tmp.numel(),
+                                                       _pp(params), _stream(keys.device, stream)))
+    return out
+
+
+# ------------------------------------------------------------ single steps --
+def radix_histogram(keys, digit_bits: int = 8, *, stream=None):
+    """(hist, bases): uint64-valued int64 tensors of shape (passes, 2**digit_bits)."""
+    torch = _torch()
+    keys = _key_tensor(keys)
+    code = dtype_code(keys.dtype)
+    passes = (8 * keys.element_size() + digit_bits - 1) // digit_bits
+    hist = torch.empty((passes, 1 << digit_bits), dtype=torch.int64, device=keys.device)
+    bases = torch.empty_like(hist)
+    with torch.cuda.device(keys.device):
+        _check("evosort_radix_histogram",
+               _lib.evosort_radix_histogram(code, _ptr(keys), keys.numel(), digit_bits, _ptr(hist), _ptr(bases),
+                                            None, 0, _stream(keys.device, stream)))
+    return hist, bases
+
+
+def radix_pass(keys, values=None, *, pass_index: int, params: Params | None = None, stream=None):
+    """One stable LSD pass on digit ``pass_index``: returns (keys_out, values_out or None)."""
+    torch = _torch()
+    keys = _key_tensor(keys)
+    code = dtype_code(keys.dtype)
+    n = keys.numel()
+    vb = 0 if values is None else _key_tensor(values, "values").element_size()
+    op = OP_SORT_PAIRS if vb else OP_SORT
+    kout = torch.empty_like(keys)
+    vout = torch.empty_like(values) if vb else None
+    tmp = _temp(temp_bytes(op, code, n, vb, params), keys.device)
+    with torch.cuda.device(keys.device):
+        _check("evosort_radix_pass",
+               _lib.evosort_radix_pass(code, _ptr(keys), _ptr(kout), _ptr(values) if vb else None,
+                                       _ptr(vout) if vb else None, vb, n, pass_index, _ptr(tmp), tmp.numel(),
+                                       _pp(params), _stream(keys.device, stream)))
+    return kout, vout
+
+
+def merge_block_sort(keys, values=None, *, params: Params | None = None, stream=None):
+    """Mergesort block sort: returns (keys_out, values_out or None, run_length)."""
+    torch = _torch()
+    keys = _key_tensor(keys)
+    code = dtype_code(keys.dtype)
+    n = keys.numel()
+    vb = 0 if values is None else _key_tensor(values, "values").element_size()
+    kout = torch.empty_like(keys)
+    vout = torch.empty_like(values) if vb else None
+    run = _i64(0)
+    with torch.cuda.device(keys.device):
+        _check("evosort_merge_block_sort",
+               _lib.evosort_merge_block_sort(code, _ptr(keys), _ptr(kout), _ptr(values) if vb else None,
+                                             _ptr(vout) if vb else None, vb, n, _pp(params), ctypes.byref(run),
+                                             _stream(keys.device, stream)))
+    return kout, vout, int(run.value)
+
+
+def merge_round(keys, values=None, *, run: int, stream=None):
+    """One merge round over pairs of sorted runs of length ``run``: returns (keys_out, values_out or None)."""
+    torch = _torch()
+    keys = _key_tensor(keys)
+    code = dtype_code(keys.dtype)
+    n = keys.numel()
+    vb = 0 if values is None else _key_tensor(values, "values").element_size()
+    op = OP_SORT_PAIRS if vb else OP_SORT
+    kout = torch.empty_like(keys)
+    vout = torch.empty_like(values) if vb else None
+    tmp = _temp(256 + 8 * (n + 4), keys.device)
+    with torch.cuda.device(keys.device):
+        _check("evosort_merge_round",
+               _lib.evosort_merge_round(code, _ptr(keys), _ptr(kout), _ptr(values) if vb else None,
+                                        _ptr(vout) if vb else None, vb, n, run, _ptr(tmp), tmp.numel(),
+                                        _stream(keys.device, stream)))
+    return kout, vout
+
+
+def check_device_error(temp, *, stream=None) -> int:
+    """Synchronize and read the error word a radix call left in ``temp``: a status code."""
+    torch = _torch()
+    with torch.cuda.device(temp.device):
+        return _lib.evosort_check_device_error(_ptr(temp), temp.numel(), _stream(temp.device, stream))
+
+
+# --------------------------------------------------------------- profiling --
+def profile_enable(on: bool = True):
+    _lib.evosort_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    _lib.evosort_profile_reset()
+
+
+def profile_collect() -> dict:
+    """{kernel name: (launches, total milliseconds)} for every launch since the last reset."""
+    count = _lib.evosort_profile_collect()
+    out = {}
+    name = ctypes.create_string_buffer(128)
+    for i in range(count):
+        launches = ctypes.c_uint64(0)
+        ms = ctypes.c_double(0.0)
+        _check("evosort_profile_get", _lib.evosort_profile_get(i, name, 128, ctypes.byref(launches),
+                                                               ctypes.byref(ms)))
+        out[name.value.decode()] = (int(launches.value), float(ms.value))
+    return out

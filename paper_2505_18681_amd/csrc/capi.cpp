@@ -1,0 +1,877 @@
+// C ABI of the sort library: argument checks, the adaptive partition sort
+// dispatch (Sec. 4.3, Algorithm 6), scratch layout, and the launch sequences
+// of the radix, mergesort and one-workgroup routines.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "evosort.h"
+#include "kernels.hpp"
+#include "merge.hpp"
+#include "radix_shapes.hpp"
+#include "small_sort.hpp"
+
+using namespace evosort;
+
+namespace {
+
+thread_local int t_last_hip = 0;
+
+constexpr uint32_t kDefaultSpinLimit = 1u << 24;
+constexpr uint32_t kDefaultInsertion = 8;
+constexpr size_t kAlign = 256;
+constexpr int64_t kStatus32Limit = (int64_t)1 << 30;  // 32-bit look-back words hold counts < 2^30
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+bool key_desc(int dtype, KeyDesc* kd, bool* is_int)
+{
+    switch (dtype) {
+    case EVOSORT_INT32:
+        *kd = {4, 0x80000000ull, 0};
+        *is_int = true;
+        return true;
+    case EVOSORT_UINT32:
+        *kd = {4, 0, 0};
+        *is_int = true;
+        return true;
+    case EVOSORT_FLOAT32:
+        *kd = {4, 0x80000000ull, 0xffffffffull};
+        *is_int = false;
+        return true;
+    case EVOSORT_INT64:
+        *kd = {8, 0x8000000000000000ull, 0};
+        *is_int = true;
+        return true;
+    case EVOSORT_FLOAT64:
+        *kd = {8, 0x8000000000000000ull, ~0ull};
+        *is_int = false;
+        return true;
+    default:
+        return false;
+    }
+}
+
+// --------------------------------------------------------------- profiling --
+struct ProfRecord {
+    const char* name;
+    hipEvent_t start;
+    hipEvent_t stop;
+};
+
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<ProfRecord> pending;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::string> names;
+    std::map<std::string, std::pair<uint64_t, double>> totals;
+
+    hipEvent_t get_event()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess)
+            return nullptr;
+        return e;
+    }
+};
+
+Profiler& prof()
+{
+    static Profiler* p = new Profiler();  // never destroyed: events outlive static teardown order
+    return *p;
+}
+
+// Runs one kernel launch, bracketed by events when profiling is on.
+template <class F>
+hipError_t timed(const char* name, hipStream_t s, F&& launch)
+{
+    Profiler& P = prof();
+    bool on;
+    {
+        std::lock_guard<std::mutex> g(P.mu);
+        on = P.on;
+    }
+    if (!on)
+        return launch();
+    hipEvent_t a, b;
+    {
+        std::lock_guard<std::mutex> g(P.mu);
+        a = P.get_event();
+        b = P.get_event();
+    }
+    if (!a || !b)
+        return launch();
+    hipEventRecord(a, s);
+    hipError_t e = launch();
+    hipEventRecord(b, s);
+    std::lock_guard<std::mutex> g(P.mu);
+    P.pending.push_back({name, a, b});
+    return e;
+}
+
+// ------------------------------------------------------------------ plan ----
+struct Plan {
+    evosort_plan_info info;
+    KeyDesc kd;
+    bool is_int;
+    int op;
+    int64_t n;
+    int vb;  // value or index bytes
+    int bits;
+    RadixShape shape;
+    uint32_t spin_limit;
+    uint32_t debug_flags;
+    uint32_t t_ins;
+    // radix scratch layout (byte offsets into temp)
+    size_t off_keys_a, off_keys_b, off_vals, off_hist, off_bases, off_status, off_ctr, off_err;
+    size_t zero_begin, zero_end;
+    size_t status_pass_bytes;
+    // merge scratch layout
+    MergePlan mp;
+    size_t off_mkeys, off_mkeys2, off_mvals, off_parts;
+    size_t total;
+};
+
+evosort_status check_params(const evosort_params* p)
+{
+    if (p->struct_size != sizeof(evosort_params))
+        return EVOSORT_ERR_INVALID_ARG;
+    if (p->algo != EVOSORT_ALGO_AUTO && p->algo != EVOSORT_ALGO_MERGE && p->algo != EVOSORT_ALGO_RADIX)
+        return EVOSORT_ERR_INVALID_ARG;
+    if (p->digit_bits < 4 || p->digit_bits > 12)
+        return EVOSORT_ERR_INVALID_ARG;
+    if (p->insertion_threshold < 1 || p->insertion_threshold > 2048)
+        return EVOSORT_ERR_INVALID_ARG;
+    if ((p->block_threads == 0) != (p->items_per_thread == 0))
+        return EVOSORT_ERR_INVALID_ARG;
+    return EVOSORT_OK;
+}
+
+void default_params(evosort_params* p)
+{
+    memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(evosort_params);
+    p->algo = EVOSORT_ALGO_AUTO;
+    p->digit_bits = 8;
+    p->insertion_threshold = kDefaultInsertion;
+    p->fallback_threshold = (uint64_t)kSmallCapacity4;
+    p->block_threads = 0;
+    p->items_per_thread = 0;
+    p->spin_limit = 0;
+    p->debug_flags = 0;
+}
+
+enum ForcePath { FORCE_NONE = 0, FORCE_RADIX = 1, FORCE_MERGE = 2 };
+
+evosort_status make_plan(int op, int dtype, int64_t n, uint32_t value_bytes, const evosort_params* pin, Plan* P,
+                         ForcePath force = FORCE_NONE)
+{
+    memset(P, 0, sizeof(*P));
+    evosort_params p;
+    if (pin) {
+        p = *pin;
+        evosort_status st = check_params(&p);
+        if (st != EVOSORT_OK)
+            return st;
+    } else {
+        default_params(&p);
+    }
+    if (n < 0)
+        return EVOSORT_ERR_INVALID_ARG;
+    if (op != EVOSORT_OP_SORT && op != EVOSORT_OP_SORT_PAIRS && op != EVOSORT_OP_ARGSORT)
+        return EVOSORT_ERR_INVALID_ARG;
+    if (!key_desc(dtype, &P->kd, &P->is_int))
+        return EVOSORT_ERR_UNSUPPORTED_DTYPE;
+    if (op == EVOSORT_OP_SORT) {
+        if (value_bytes != 0)
+            return EVOSORT_ERR_INVALID_ARG;
+    } else if (value_bytes != 4 && value_bytes != 8) {
+        return EVOSORT_ERR_UNSUPPORTED_DTYPE;
+    }
+    if (op == EVOSORT_OP_ARGSORT && value_bytes == 4 && n > 0x7fffffffLL)
+        return EVOSORT_ERR_INVALID_ARG;
+
+    const int kb = P->kd.bytes;
+    const int vb = (int)value_bytes;
+    P->op = op;
+    P->n = n;
+    P->vb = vb;
+    P->bits = (int)p.digit_bits;
+    P->spin_limit = p.spin_limit ? p.spin_limit : kDefaultSpinLimit;
+    P->debug_flags = p.debug_flags;
+    P->t_ins = p.insertion_threshold;
+    P->shape = p.block_threads ? RadixShape{(int)p.block_threads, (int)p.items_per_thread}
+                               : radix_default_shape(kb, vb);
+    const int64_t cap = small_sort_capacity(kb, vb);
+    P->info.small_capacity = (uint64_t)cap;
+    P->info.digit_bits = p.digit_bits;
+    P->info.block_threads = (uint32_t)P->shape.threads;
+    P->info.items_per_thread = (uint32_t)P->shape.items;
+
+    // The adaptive partition sort (Sec. 4.3, Algorithm 6), with the readings
+    // of the GPU library: the small-array branch is capped by one
+    // workgroup's capacity; float keys take the radix branch too; A_code 0
+    // means radix.
+    int path;
+    if (force == FORCE_RADIX)
+        path = EVOSORT_PATH_RADIX;
+    else if (force == FORCE_MERGE)
+        path = EVOSORT_PATH_MERGE;
+    else if (n <= 1)
+        path = EVOSORT_PATH_COPY;
+    else if ((uint64_t)n < p.fallback_threshold && n <= cap)
+        path = EVOSORT_PATH_SMALL;
+    else if (p.algo == EVOSORT_ALGO_MERGE)
+        path = EVOSORT_PATH_MERGE;
+    else
+        path = EVOSORT_PATH_RADIX;
+    P->info.path = path;
+
+    // Scratch layouts.  Both start with a 256-byte header whose first word is
+    // the device error word (evosort_check_device_error reads it there).
+    size_t off = 0;
+    if (path == EVOSORT_PATH_RADIX) {
+        const int passes = (8 * kb + P->bits - 1) / P->bits;
+        const int status_bytes = n < kStatus32Limit ? 4 : 8;
+        if (!radix_pass_available(kb, vb, P->bits, P->shape, status_bytes))
+            return EVOSORT_ERR_UNSUPPORTED_PARAM;
+        const uint64_t tile = (uint64_t)P->shape.threads * P->shape.items;
+        const uint64_t tiles = ((uint64_t)n + tile - 1) / tile;
+        if (tiles > 0xffffffffull)
+            return EVOSORT_ERR_INVALID_ARG;
+        const size_t bins = (size_t)1 << P->bits;
+        P->info.passes = (uint32_t)passes;
+        P->info.status_bytes = (uint32_t)status_bytes;
+        P->info.tile_keys = tile;
+        P->info.tiles = tiles;
+        // zeroed on every call: header (error word, tile counters), histograms, look-back words
+        P->zero_begin = 0;
+        P->off_err = 0;
+        P->off_ctr = 16;  // passes * 4 <= 64 bytes
+        off = kAlign;
+        P->off_hist = off;
+        off = align_up(off + (size_t)passes * bins * 8);
+        P->status_pass_bytes = align_up((size_t)tiles * bins * status_bytes);
+        P->off_status = off;
+        off += (size_t)passes * P->status_pass_bytes;
+        P->zero_end = off;
+        P->off_bases = off;
+        off = align_up(off + (size_t)passes * bins * 8);
+        P->off_keys_a = off;
+        off = align_up(off + (size_t)n * kb);
+        if (op == EVOSORT_OP_ARGSORT) {
+            P->off_keys_b = off;
+            off = align_up(off + (size_t)n * kb);
+        }
+        if (vb) {
+            P->off_vals = off;
+            off = align_up(off + (size_t)n * vb);
+        }
+    } else if (path == EVOSORT_PATH_MERGE) {
+        P->mp = merge_plan(kb, vb, n, P->t_ins);
+        P->info.tile_keys = P->mp.block_keys;
+        P->info.tiles = P->mp.blocks;
+        P->info.merge_rounds = P->mp.rounds;
+        P->info.merge_block_run = P->mp.block_run;
+        P->off_err = 0;
+        off = kAlign;
+        P->off_mkeys = off;
+        off = align_up(off + (size_t)n * kb);
+        if (op == EVOSORT_OP_ARGSORT) {
+            P->off_mkeys2 = off;
+            off = align_up(off + (size_t)n * kb);
+        }
+        if (vb) {
+            P->off_mvals = off;
+            off = align_up(off + (size_t)n * vb);
+        }
+        P->off_parts = off;
+        off = align_up(off + merge_partition_bytes(P->mp));
+    }
+    P->total = off;
+    P->info.temp_bytes = off;
+    return EVOSORT_OK;
+}
+
+// ------------------------------------------------------------ arg checks ----
+bool overlaps(const void* a, size_t an, const void* b, size_t bn)
+{
+    if (!a || !b || an == 0 || bn == 0)
+        return false;
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bn && y < x + an;
+}
+
+// Distinct buffers must not overlap; pairs listed in `same_ok` may be equal.
+evosort_status check_buffers(const void* const* bufs, const size_t* sizes, int count, int same_ok_a1, int same_ok_b1,
+                             int same_ok_a2, int same_ok_b2)
+{
+    for (int i = 0; i < count; ++i)
+        for (int j = i + 1; j < count; ++j) {
+            if (!bufs[i] || !bufs[j])
+                continue;
+            const bool ok_pair = (i == same_ok_a1 && j == same_ok_b1) || (i == same_ok_a2 && j == same_ok_b2);
+            if (ok_pair && bufs[i] == bufs[j])
+                continue;
+            if (overlaps(bufs[i], sizes[i], bufs[j], sizes[j]))
+                return EVOSORT_ERR_INVALID_ARG;
+        }
+    return EVOSORT_OK;
+}
+
+evosort_status hip_fail(hipError_t e)
+{
+    t_last_hip = (int)e;
+    return EVOSORT_ERR_HIP;
+}
+
+#define EVOSORT_LAUNCH(name, s, expr)                         \
+    do {                                                      \
+        hipError_t e_ = timed((name), (s), [&] { return (expr); }); \
+        if (e_ != hipSuccess)                                 \
+            return hip_fail(e_);                              \
+    } while (0)
+
+unsigned char* at(void* temp, size_t off) { return reinterpret_cast<unsigned char*>(temp) + off; }
+
+// ------------------------------------------------------------ radix path ----
+// Buffers: src keys (read only), out keys (may equal src), keys_a/keys_b in
+// temp; values likewise.  The pass buffers alternate so that the last pass
+// lands in the output; an odd pass count sorted in place needs one copy.
+evosort_status run_radix(const Plan& P, const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
+                         void* temp, hipStream_t s)
+{
+    const int kb = P.kd.bytes, vb = P.vb;
+    const int passes = (int)P.info.passes;
+    const size_t bins = (size_t)1 << P.bits;
+    const int64_t n = P.n;
+    auto* hist = reinterpret_cast<uint64_t*>(at(temp, P.off_hist));
+    auto* bases = reinterpret_cast<uint64_t*>(at(temp, P.off_bases));
+    auto* ctr = reinterpret_cast<uint32_t*>(at(temp, P.off_ctr));
+    auto* err = reinterpret_cast<uint32_t*>(at(temp, P.off_err));
+
+    EVOSORT_LAUNCH("fill_zero", s, launch_fill_zero(at(temp, P.zero_begin), P.zero_end - P.zero_begin, s));
+    EVOSORT_LAUNCH("radix_histogram", s, launch_radix_histogram(P.kd, keys_in, n, P.bits, passes, hist, s));
+    EVOSORT_LAUNCH("radix_scan", s, launch_radix_scan(hist, bases, P.bits, passes, s));
+
+    const bool argsort = P.op == EVOSORT_OP_ARGSORT;
+    void* ta = at(temp, P.off_keys_a);
+    void* tb = argsort ? at(temp, P.off_keys_b) : nullptr;
+    void* tv = vb ? at(temp, P.off_vals) : nullptr;
+
+    // Destination of pass p: alternate between X and Y where the last pass
+    // writes the output.  For keys: X = out, Y = temp (argsort: temp a/b).
+    const bool in_place_keys = !argsort && keys_out == keys_in;
+    const bool in_place_vals = P.op == EVOSORT_OP_SORT_PAIRS && vals_out == vals_in;
+    // With the last pass writing `out`, pass 0 writes `out` iff passes is odd.
+    // Writing `out` in pass 0 is not allowed when it aliases the input.
+    const bool odd = (passes & 1) != 0;
+    const bool extra_copy = odd && (in_place_keys || in_place_vals);
+
+    const void* ksrc = keys_in;
+    const void* vsrc = vals_in;
+    for (int p = 0; p < passes; ++p) {
+        const bool last = p == passes - 1;
+        // parity: which buffer this pass writes
+        const bool to_out = extra_copy ? false : (((passes - 1 - p) & 1) == 0);
+        void* kdst;
+        void* vdst = nullptr;
+        if (argsort) {
+            kdst = (p & 1) ? tb : ta;  // keys never reach an output
+            vdst = to_out ? vals_out : tv;
+        } else {
+            kdst = to_out ? keys_out : ta;
+            if (extra_copy)
+                kdst = (p & 1) ? keys_out : ta;
+            if (vb) {
+                vdst = to_out ? vals_out : tv;
+                if (extra_copy)
+                    vdst = (p & 1) ? vals_out : tv;
+            }
+        }
+        RadixPassArgs a{};
+        a.keys_in = ksrc;
+        a.keys_out = kdst;
+        a.vals_in = vsrc;
+        a.vals_out = vdst;
+        a.n = n;
+        a.shift = (uint32_t)(p * P.bits);
+        a.bases = bases + (size_t)p * bins;
+        a.status = at(temp, P.off_status + (size_t)p * P.status_pass_bytes);
+        a.tile_counter = ctr + p;
+        a.error_word = err;
+        a.flags = 0;
+        if (argsort && p == 0)
+            a.flags |= RADIX_FLAG_IOTA;
+        if (argsort && last)
+            a.flags |= RADIX_FLAG_SKIP_KEYS;
+        if (P.debug_flags & EVOSORT_DEBUG_WITHHOLD_TILE0)
+            a.flags |= RADIX_FLAG_WITHHOLD_T0;
+        a.spin_limit = P.spin_limit;
+        a.tiles = (uint32_t)P.info.tiles;
+        EVOSORT_LAUNCH("radix_pass", s,
+                       launch_radix_pass(P.kd, vb, P.bits, P.shape, (int)P.info.status_bytes, a,
+                                         (uint32_t)P.info.tiles, s));
+        ksrc = kdst;
+        vsrc = vdst;
+    }
+    if (extra_copy) {
+        // odd pass count, in place: the last pass wrote temp
+        EVOSORT_LAUNCH("copy", s, launch_copy(keys_out, ksrc, (size_t)n * kb, s));
+        if (vb)
+            EVOSORT_LAUNCH("copy", s, launch_copy(vals_out, vsrc, (size_t)n * vb, s));
+    }
+    return EVOSORT_OK;
+}
+
+evosort_status run_small(const Plan& P, const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
+                         hipStream_t s)
+{
+    SmallSortArgs a{};
+    a.keys_in = keys_in;
+    a.keys_out = keys_out;
+    a.vals_in = vals_in;
+    a.vals_out = vals_out;
+    a.n = P.n;
+    a.mode = P.op == EVOSORT_OP_SORT ? SMALL_MODE_KEYS
+                                     : (P.op == EVOSORT_OP_SORT_PAIRS ? SMALL_MODE_PAIRS : SMALL_MODE_ARGSORT);
+    EVOSORT_LAUNCH("small_sort", s, launch_small_sort(P.kd, P.vb, a, s));
+    return EVOSORT_OK;
+}
+
+evosort_status run_copy(const Plan& P, const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
+                        hipStream_t s)
+{
+    const size_t n = (size_t)P.n;
+    if (P.op == EVOSORT_OP_ARGSORT) {
+        if (n == 1) {
+            // the one index is 0
+            EVOSORT_LAUNCH("fill_zero", s, launch_fill_zero(vals_out, (size_t)P.vb, s));
+        }
+        return EVOSORT_OK;
+    }
+    EVOSORT_LAUNCH("copy", s, launch_copy(keys_out, keys_in, n * P.kd.bytes, s));
+    if (P.op == EVOSORT_OP_SORT_PAIRS)
+        EVOSORT_LAUNCH("copy", s, launch_copy(vals_out, vals_in, n * P.vb, s));
+    return EVOSORT_OK;
+}
+
+evosort_status run_merge(const Plan& P, const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
+                         void* temp, hipStream_t s)
+{
+    MergeBuffers b{};
+    b.keys_in = keys_in;
+    b.keys_out = keys_out;
+    b.vals_in = vals_in;
+    b.vals_out = vals_out;
+    b.keys_tmp = at(temp, P.off_mkeys);
+    b.keys_tmp2 = P.op == EVOSORT_OP_ARGSORT ? at(temp, P.off_mkeys2) : nullptr;
+    b.vals_tmp = P.vb ? at(temp, P.off_mvals) : nullptr;
+    b.parts = reinterpret_cast<int64_t*>(at(temp, P.off_parts));
+    b.iota = P.op == EVOSORT_OP_ARGSORT;
+    MergeLaunch ml;
+    ml.block_sort = [&](const MergeBlockArgs& a) -> hipError_t {
+        return timed("merge_block_sort", s, [&] { return launch_merge_block_sort(P.kd, P.vb, P.mp, a, s); });
+    };
+    ml.partition = [&](const MergeRoundArgs& a) -> hipError_t {
+        return timed("merge_partition", s, [&] { return launch_merge_partition(P.kd, P.mp, a, s); });
+    };
+    ml.merge = [&](const MergeRoundArgs& a) -> hipError_t {
+        return timed("merge_round", s, [&] { return launch_merge_round(P.kd, P.vb, P.mp, a, s); });
+    };
+    hipError_t e = run_merge_sort(P.mp, b, ml);
+    if (e != hipSuccess)
+        return hip_fail(e);
+    return EVOSORT_OK;
+}
+
+evosort_status sort_common(int op, int dtype, const void* keys_in, void* keys_out, const void* vals_in,
+                           void* vals_out, uint32_t vb, int64_t n, void* temp, size_t temp_bytes,
+                           const evosort_params* p, void* stream)
+{
+    Plan P;
+    evosort_status st = make_plan(op, dtype, n, vb, p, &P);
+    if (st != EVOSORT_OK)
+        return st;
+    if (n == 0)
+        return EVOSORT_OK;
+    const size_t kbytes = (size_t)n * P.kd.bytes;
+    const size_t vbytes = (size_t)n * vb;
+    if (!keys_in)
+        return EVOSORT_ERR_INVALID_ARG;
+    if (op != EVOSORT_OP_ARGSORT && !keys_out)
+        return EVOSORT_ERR_INVALID_ARG;
+    if (op == EVOSORT_OP_SORT_PAIRS && (!vals_in || !vals_out))
+        return EVOSORT_ERR_INVALID_ARG;
+    if (op == EVOSORT_OP_ARGSORT && !vals_out)
+        return EVOSORT_ERR_INVALID_ARG;
+    if (temp_bytes < P.total)
+        return EVOSORT_ERR_TEMP_TOO_SMALL;
+    if (P.total > 0 && (!temp || ((uintptr_t)temp & (kAlign - 1))))
+        return EVOSORT_ERR_INVALID_ARG;
+    // buffers: 0 keys_in, 1 keys_out, 2 vals_in, 3 vals_out, 4 temp
+    const void* bufs[5] = {keys_in, op == EVOSORT_OP_ARGSORT ? nullptr : keys_out,
+                           op == EVOSORT_OP_SORT_PAIRS ? vals_in : nullptr, op == EVOSORT_OP_SORT ? nullptr : vals_out,
+                           P.total ? temp : nullptr};
+    const size_t sizes[5] = {kbytes, kbytes, vbytes, vbytes, P.total};
+    st = check_buffers(bufs, sizes, 5, 0, 1, 2, 3);
+    if (st != EVOSORT_OK)
+        return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    switch (P.info.path) {
+    case EVOSORT_PATH_COPY:
+        return run_copy(P, keys_in, keys_out, vals_in, vals_out, s);
+    case EVOSORT_PATH_SMALL:
+        return run_small(P, keys_in, keys_out, vals_in, vals_out, s);
+    case EVOSORT_PATH_RADIX:
+        return run_radix(P, keys_in, keys_out, vals_in, vals_out, temp, s);
+    case EVOSORT_PATH_MERGE:
+        return run_merge(P, keys_in, keys_out, vals_in, vals_out, temp, s);
+    default:
+        return EVOSORT_ERR_INVALID_ARG;
+    }
+}
+
+}  // namespace
+
+// ===================================================================== ABI ===
+extern "C" {
+
+void evosort_default_params(evosort_params* p)
+{
+    if (p)
+        default_params(p);
+}
+
+evosort_status evosort_temp_bytes(int op, int dtype, int64_t n, uint32_t value_bytes, const evosort_params* p,
+                                  size_t* out_bytes)
+{
+    if (!out_bytes)
+        return EVOSORT_ERR_INVALID_ARG;
+    Plan P;
+    evosort_status st = make_plan(op, dtype, n, value_bytes, p, &P);
+    if (st != EVOSORT_OK)
+        return st;
+    // Step functions of both routines run on the same scratch.
+    Plan R, M;
+    size_t need = P.total;
+    if (n > 0 && make_plan(op, dtype, n, value_bytes, p, &R, FORCE_RADIX) == EVOSORT_OK && R.total > need)
+        need = R.total;
+    if (n > 0 && make_plan(op, dtype, n, value_bytes, p, &M, FORCE_MERGE) == EVOSORT_OK && M.total > need)
+        need = M.total;
+    *out_bytes = need;
+    return EVOSORT_OK;
+}
+
+evosort_status evosort_plan(int op, int dtype, int64_t n, uint32_t value_bytes, const evosort_params* p,
+                            evosort_plan_info* out)
+{
+    if (!out)
+        return EVOSORT_ERR_INVALID_ARG;
+    Plan P;
+    evosort_status st = make_plan(op, dtype, n, value_bytes, p, &P);
+    if (st != EVOSORT_OK)
+        return st;
+    *out = P.info;
+    size_t need = 0;
+    evosort_temp_bytes(op, dtype, n, value_bytes, p, &need);
+    out->temp_bytes = need;
+    return EVOSORT_OK;
+}
+
+evosort_status evosort_sort(int dtype, const void* keys_in, void* keys_out, int64_t n, void* temp, size_t temp_bytes,
+                            const evosort_params* p, void* stream)
+{
+    return sort_common(EVOSORT_OP_SORT, dtype, keys_in, keys_out, nullptr, nullptr, 0, n, temp, temp_bytes, p,
+                       stream);
+}
+
+evosort_status evosort_sort_pairs(int dtype, const void* keys_in, void* keys_out, const void* vals_in,
+                                  void* vals_out, uint32_t value_bytes, int64_t n, void* temp, size_t temp_bytes,
+                                  const evosort_params* p, void* stream)
+{
+    return sort_common(EVOSORT_OP_SORT_PAIRS, dtype, keys_in, keys_out, vals_in, vals_out, value_bytes, n, temp,
+                       temp_bytes, p, stream);
+}
+
+evosort_status evosort_argsort(int dtype, const void* keys_in, void* idx_out, uint32_t index_bytes, int64_t n,
+                               void* temp, size_t temp_bytes, const evosort_params* p, void* stream)
+{
+    return sort_common(EVOSORT_OP_ARGSORT, dtype, keys_in, nullptr, nullptr, idx_out, index_bytes, n, temp,
+                       temp_bytes, p, stream);
+}
+
+evosort_status evosort_radix_histogram(int dtype, const void* keys, int64_t n, uint32_t digit_bits,
+                                       uint64_t* hist_out, uint64_t* bases_out, void* temp, size_t temp_bytes,
+                                       void* stream)
+{
+    (void)temp;
+    (void)temp_bytes;
+    KeyDesc kd;
+    bool is_int;
+    if (!key_desc(dtype, &kd, &is_int))
+        return EVOSORT_ERR_UNSUPPORTED_DTYPE;
+    if (n < 0 || digit_bits < 4 || digit_bits > 12 || !hist_out || (n > 0 && !keys))
+        return EVOSORT_ERR_INVALID_ARG;
+    const int bits = (int)digit_bits;
+    const int passes = (8 * kd.bytes + bits - 1) / bits;
+    const size_t row_bytes = (size_t)passes * ((size_t)1 << bits) * 8;
+    if (overlaps(hist_out, row_bytes, keys, (size_t)n * kd.bytes) ||
+        (bases_out && (overlaps(bases_out, row_bytes, keys, (size_t)n * kd.bytes) ||
+                       overlaps(bases_out, row_bytes, hist_out, row_bytes))))
+        return EVOSORT_ERR_INVALID_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // hist_out is zeroed and filled directly (row_bytes is a multiple of 16)
+    EVOSORT_LAUNCH("fill_zero", s, launch_fill_zero(hist_out, row_bytes, s));
+    if (n > 0)
+        EVOSORT_LAUNCH("radix_histogram", s, launch_radix_histogram(kd, keys, n, bits, passes, hist_out, s));
+    if (bases_out)
+        EVOSORT_LAUNCH("radix_scan", s, launch_radix_scan(hist_out, bases_out, bits, passes, s));
+    return EVOSORT_OK;
+}
+
+evosort_status evosort_radix_pass(int dtype, const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
+                                  uint32_t value_bytes, int64_t n, uint32_t pass, void* temp, size_t temp_bytes,
+                                  const evosort_params* p, void* stream)
+{
+    const int op = value_bytes ? EVOSORT_OP_SORT_PAIRS : EVOSORT_OP_SORT;
+    Plan P;
+    evosort_status st = make_plan(op, dtype, n, value_bytes, p, &P, FORCE_RADIX);
+    if (st != EVOSORT_OK)
+        return st;
+    if (pass >= P.info.passes)
+        return EVOSORT_ERR_INVALID_ARG;
+    if (n == 0)
+        return EVOSORT_OK;
+    if (!keys_in || !keys_out || (value_bytes && (!vals_in || !vals_out)))
+        return EVOSORT_ERR_INVALID_ARG;
+    if (temp_bytes < P.total)
+        return EVOSORT_ERR_TEMP_TOO_SMALL;
+    if (!temp || ((uintptr_t)temp & (kAlign - 1)))
+        return EVOSORT_ERR_INVALID_ARG;
+    const size_t kbytes = (size_t)n * P.kd.bytes, vbytes = (size_t)n * value_bytes;
+    const void* bufs[5] = {keys_in, keys_out, value_bytes ? vals_in : nullptr, value_bytes ? vals_out : nullptr, temp};
+    const size_t sizes[5] = {kbytes, kbytes, vbytes, vbytes, P.total};
+    st = check_buffers(bufs, sizes, 5, -1, -1, -1, -1);
+    if (st != EVOSORT_OK)
+        return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const size_t bins = (size_t)1 << P.bits;
+    auto* hist = reinterpret_cast<uint64_t*>(at(temp, P.off_hist));
+    auto* bases = reinterpret_cast<uint64_t*>(at(temp, P.off_bases));
+    EVOSORT_LAUNCH("fill_zero", s, launch_fill_zero(at(temp, P.zero_begin), P.zero_end - P.zero_begin, s));
+    EVOSORT_LAUNCH("radix_histogram", s,
+                   launch_radix_histogram(P.kd, keys_in, n, P.bits, (int)P.info.passes, hist, s));
+    EVOSORT_LAUNCH("radix_scan", s, launch_radix_scan(hist, bases, P.bits, (int)P.info.passes, s));
+    RadixPassArgs a{};
+    a.keys_in = keys_in;
+    a.keys_out = keys_out;
+    a.vals_in = vals_in;
+    a.vals_out = vals_out;
+    a.n = n;
+    a.shift = pass * (uint32_t)P.bits;
+    a.bases = bases + (size_t)pass * bins;
+    a.status = at(temp, P.off_status);
+    a.tile_counter = reinterpret_cast<uint32_t*>(at(temp, P.off_ctr));
+    a.error_word = reinterpret_cast<uint32_t*>(at(temp, P.off_err));
+    a.flags = (P.debug_flags & EVOSORT_DEBUG_WITHHOLD_TILE0) ? RADIX_FLAG_WITHHOLD_T0 : 0u;
+    a.spin_limit = P.spin_limit;
+    a.tiles = (uint32_t)P.info.tiles;
+    EVOSORT_LAUNCH("radix_pass", s,
+                   launch_radix_pass(P.kd, (int)value_bytes, P.bits, P.shape, (int)P.info.status_bytes, a,
+                                     (uint32_t)P.info.tiles, s));
+    return EVOSORT_OK;
+}
+
+evosort_status evosort_merge_block_sort(int dtype, const void* keys_in, void* keys_out, const void* vals_in,
+                                        void* vals_out, uint32_t value_bytes, int64_t n, const evosort_params* p,
+                                        int64_t* run_out, void* stream)
+{
+    const int op = value_bytes ? EVOSORT_OP_SORT_PAIRS : EVOSORT_OP_SORT;
+    Plan P;
+    evosort_status st = make_plan(op, dtype, n, value_bytes, p, &P, FORCE_MERGE);
+    if (st != EVOSORT_OK)
+        return st;
+    if (run_out)
+        *run_out = (int64_t)P.mp.block_run;
+    if (n == 0)
+        return EVOSORT_OK;
+    if (!keys_in || !keys_out || (value_bytes && (!vals_in || !vals_out)))
+        return EVOSORT_ERR_INVALID_ARG;
+    const size_t kbytes = (size_t)n * P.kd.bytes, vbytes = (size_t)n * value_bytes;
+    const void* bufs[4] = {keys_in, keys_out, value_bytes ? vals_in : nullptr, value_bytes ? vals_out : nullptr};
+    const size_t sizes[4] = {kbytes, kbytes, vbytes, vbytes};
+    st = check_buffers(bufs, sizes, 4, -1, -1, -1, -1);
+    if (st != EVOSORT_OK)
+        return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    MergeBlockArgs a{};
+    a.keys_in = keys_in;
+    a.keys_out = keys_out;
+    a.vals_in = vals_in;
+    a.vals_out = vals_out;
+    a.n = n;
+    a.iota = false;
+    a.skip_keys = false;
+    EVOSORT_LAUNCH("merge_block_sort", s, launch_merge_block_sort(P.kd, (int)value_bytes, P.mp, a, s));
+    return EVOSORT_OK;
+}
+
+evosort_status evosort_merge_round(int dtype, const void* keys_in, void* keys_out, const void* vals_in,
+                                   void* vals_out, uint32_t value_bytes, int64_t n, int64_t run, void* temp,
+                                   size_t temp_bytes, void* stream)
+{
+    const int op = value_bytes ? EVOSORT_OP_SORT_PAIRS : EVOSORT_OP_SORT;
+    Plan P;
+    evosort_status st = make_plan(op, dtype, n, value_bytes, nullptr, &P, FORCE_MERGE);
+    if (st != EVOSORT_OK)
+        return st;
+    if (run < 1)
+        return EVOSORT_ERR_INVALID_ARG;
+    if (n == 0)
+        return EVOSORT_OK;
+    if (!keys_in || !keys_out || (value_bytes && (!vals_in || !vals_out)))
+        return EVOSORT_ERR_INVALID_ARG;
+    // This step only needs the partition entries of its own round, placed
+    // right after the header.
+    P.mp.max_parts = merge_round_parts(P.mp, run);
+    P.off_parts = kAlign;
+    P.total = P.off_parts + merge_partition_bytes(P.mp);
+    if (temp_bytes < P.total)
+        return EVOSORT_ERR_TEMP_TOO_SMALL;
+    if (!temp || ((uintptr_t)temp & (kAlign - 1)))
+        return EVOSORT_ERR_INVALID_ARG;
+    const size_t kbytes = (size_t)n * P.kd.bytes, vbytes = (size_t)n * value_bytes;
+    const void* bufs[5] = {keys_in, keys_out, value_bytes ? vals_in : nullptr, value_bytes ? vals_out : nullptr, temp};
+    const size_t sizes[5] = {kbytes, kbytes, vbytes, vbytes, P.total};
+    st = check_buffers(bufs, sizes, 5, -1, -1, -1, -1);
+    if (st != EVOSORT_OK)
+        return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    MergeRoundArgs a{};
+    a.keys_in = keys_in;
+    a.keys_out = keys_out;
+    a.vals_in = vals_in;
+    a.vals_out = vals_out;
+    a.n = n;
+    a.run = run;
+    a.parts = reinterpret_cast<int64_t*>(at(temp, P.off_parts));
+    a.skip_keys = false;
+    EVOSORT_LAUNCH("merge_partition", s, launch_merge_partition(P.kd, P.mp, a, s));
+    EVOSORT_LAUNCH("merge_round", s, launch_merge_round(P.kd, (int)value_bytes, P.mp, a, s));
+    return EVOSORT_OK;
+}
+
+const char* evosort_status_string(int status)
+{
+    switch (status) {
+    case EVOSORT_OK:
+        return "ok";
+    case EVOSORT_ERR_INVALID_ARG:
+        return "invalid argument";
+    case EVOSORT_ERR_UNSUPPORTED_DTYPE:
+        return "unsupported key, value or index type";
+    case EVOSORT_ERR_UNSUPPORTED_PARAM:
+        return "unsupported parameter combination (e.g. a tile shape that is not compiled in)";
+    case EVOSORT_ERR_TEMP_TOO_SMALL:
+        return "temp buffer smaller than evosort_temp_bytes()";
+    case EVOSORT_ERR_HIP:
+        return "HIP error (see evosort_last_hip_error)";
+    case EVOSORT_ERR_DEVICE_TIMEOUT:
+        return "a device-side wait ran out of its spin limit";
+    default:
+        return "unknown status";
+    }
+}
+
+int evosort_last_hip_error(void) { return t_last_hip; }
+
+evosort_status evosort_check_device_error(const void* temp, size_t temp_bytes, void* stream)
+{
+    // Every radix and mergesort scratch layout starts with the error word.
+    if (!temp || temp_bytes < 4)
+        return EVOSORT_ERR_INVALID_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e);
+    uint32_t word = 0;
+    e = hipMemcpy(&word, temp, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return hip_fail(e);
+    return word ? EVOSORT_ERR_DEVICE_TIMEOUT : EVOSORT_OK;
+}
+
+void evosort_profile_enable(int on)
+{
+    Profiler& P = prof();
+    std::lock_guard<std::mutex> g(P.mu);
+    P.on = on != 0;
+}
+
+void evosort_profile_reset(void)
+{
+    Profiler& P = prof();
+    std::lock_guard<std::mutex> g(P.mu);
+    for (auto& r : P.pending) {
+        P.pool.push_back(r.start);
+        P.pool.push_back(r.stop);
+    }
+    P.pending.clear();
+    P.totals.clear();
+    P.names.clear();
+}
+
+int evosort_profile_collect(void)
+{
+    Profiler& P = prof();
+    std::lock_guard<std::mutex> g(P.mu);
+    for (auto& r : P.pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.stop) == hipSuccess && hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+            auto it = P.totals.find(r.name);
+            if (it == P.totals.end()) {
+                P.names.push_back(r.name);
+                P.totals[r.name] = {1, (double)ms};
+            } else {
+                it->second.first += 1;
+                it->second.second += ms;
+            }
+        }
+        P.pool.push_back(r.start);
+        P.pool.push_back(r.stop);
+    }
+    P.pending.clear();
+    return (int)P.names.size();
+}
+
+evosort_status evosort_profile_get(int i, char* name, size_t name_len, uint64_t* launches, double* total_ms)
+{
+    Profiler& P = prof();
+    std::lock_guard<std::mutex> g(P.mu);
+    if (i < 0 || i >= (int)P.names.size())
+        return EVOSORT_ERR_INVALID_ARG;
+    const std::string& nm = P.names[i];
+    if (name && name_len) {
+        strncpy(name, nm.c_str(), name_len - 1);
+        name[name_len - 1] = 0;
+    }
+    const auto& t = P.totals[nm];
+    if (launches)
+        *launches = t.first;
+    if (total_ms)
+        *total_ms = t.second;
+    return EVOSORT_OK;
+}
+
+}  // extern "C"

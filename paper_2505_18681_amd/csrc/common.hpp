@@ -1,0 +1,111 @@
+// Device helpers shared by the radix and merge kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace evosort {
+
+constexpr int kWave = 64;
+
+template <int KB>
+struct KeyWord;
+template <>
+struct KeyWord<4> {
+    using U = uint32_t;
+};
+template <>
+struct KeyWord<8> {
+    using U = uint64_t;
+};
+
+template <int VB>
+struct ValWord {
+    using T = uint32_t;  // placeholder when there are no values
+};
+template <>
+struct ValWord<8> {
+    using T = uint64_t;
+};
+
+// Order map of a key type: an unsigned word whose natural order is the key
+// order.  For a key word k with sign bit s (all-ones word when set):
+//   to_order(k) = k ^ (flip | (s & neg))
+// signed ints: flip = sign bit, neg = 0 (the paper's sign-bit XOR, Sec. 4,
+// Algorithms 4 and 5); uint32: flip = neg = 0; IEEE floats: flip = sign bit,
+// neg = all ones, so negative values are complemented (totalOrder).
+// The keys themselves are never rewritten: the map is applied on every load
+// that needs a digit or a comparison, and original bits are what gets stored.
+template <typename U>
+struct OrderMap {
+    U flip;
+    U neg;
+
+    __device__ __forceinline__ U sign_word(U k) const
+    {
+        using S = std::make_signed_t<U>;
+        return (U)((S)k >> (sizeof(U) * 8 - 1));
+    }
+    __device__ __forceinline__ U to_order(U k) const { return k ^ (flip | (sign_word(k) & neg)); }
+    // Inverse of to_order: the sign bit of an order word is set exactly for
+    // keys that were non-negative.
+    __device__ __forceinline__ U from_order(U m) const { return m ^ (flip | (~sign_word(m) & neg)); }
+};
+
+// Number of set bits of `mask` in lanes below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool pred) { return __builtin_amdgcn_ballot_w64(pred); }
+
+__device__ __forceinline__ int lane_id() { return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// Agent-scope relaxed atomics for words that other workgroups (on any XCD)
+// poll while this kernel runs.  Flag and payload share one word, so no
+// further ordering is needed.
+template <typename T>
+__device__ __forceinline__ T load_agent(const T* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void store_agent(T* p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive scan of one uint32 per thread across a workgroup of THREADS
+// threads.  `wave_tot` must hold THREADS/64 words of LDS.  Returns the
+// exclusive prefix and writes the workgroup total to *total.  Contains one
+// barrier; the caller must barrier before `wave_tot` is reused.
+template <int THREADS>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* wave_tot, uint32_t* total)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, kWave);
+        if (lane >= o)
+            x += y;
+    }
+    if (lane == kWave - 1)
+        wave_tot[w] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < THREADS / kWave; ++i) {
+        uint32_t t = wave_tot[i];
+        before += (i < w) ? t : 0u;
+        all += t;
+    }
+    *total = all;
+    return before + x - v;
+}
+
+}  // namespace evosort

@@ -1,0 +1,172 @@
+// Launchers of the radix histogram and scan kernels, the utility kernels, and
+// the dispatch of the pass kernel over (key bytes, value bytes).
+#include "radix_impl.hpp"
+#include "radix_shapes.hpp"
+
+namespace evosort {
+
+hipError_t radix_pass_dispatch_k4_v0(int, RadixShape, int, const KeyDesc&, const RadixPassArgs&, uint32_t,
+                                     hipStream_t, bool*);
+hipError_t radix_pass_dispatch_k4_v4(int, RadixShape, int, const KeyDesc&, const RadixPassArgs&, uint32_t,
+                                     hipStream_t, bool*);
+hipError_t radix_pass_dispatch_k4_v8(int, RadixShape, int, const KeyDesc&, const RadixPassArgs&, uint32_t,
+                                     hipStream_t, bool*);
+hipError_t radix_pass_dispatch_k8_v0(int, RadixShape, int, const KeyDesc&, const RadixPassArgs&, uint32_t,
+                                     hipStream_t, bool*);
+hipError_t radix_pass_dispatch_k8_v4(int, RadixShape, int, const KeyDesc&, const RadixPassArgs&, uint32_t,
+                                     hipStream_t, bool*);
+hipError_t radix_pass_dispatch_k8_v8(int, RadixShape, int, const KeyDesc&, const RadixPassArgs&, uint32_t,
+                                     hipStream_t, bool*);
+
+namespace {
+constexpr int kHistThreads = 256;
+
+int histogram_grid(int64_t n)
+{
+    // Enough workgroups to fill 256 CUs several times over; each thread then
+    // walks the keys with a grid stride.
+    int64_t want = (n + 16 * kHistThreads - 1) / (16 * kHistThreads);
+    if (want < 1)
+        want = 1;
+    if (want > 4096)
+        want = 4096;
+    return (int)want;
+}
+}  // namespace
+
+hipError_t launch_radix_histogram(const KeyDesc& kd, const void* keys, int64_t n, int bits, int passes,
+                                  uint64_t* hist, hipStream_t s)
+{
+    // LDS budget of one launch: 64 KB of 32-bit counters.  Group the passes so
+    // that each group has at least one private copy; add copies (at most one
+    // per wave) while they fit.
+    const size_t per_pass = ((size_t)1 << bits) * 4;
+    const int group = (int)((64 * 1024) / per_pass) < passes ? (int)((64 * 1024) / per_pass) : passes;
+    const int grid = histogram_grid(n);
+    auto* h = reinterpret_cast<unsigned long long*>(hist);
+    for (int p0 = 0; p0 < passes; p0 += group) {
+        const int np = passes - p0 < group ? passes - p0 : group;
+        int copies = (int)((64 * 1024) / (per_pass * np));
+        if (copies > kHistThreads / kWave)
+            copies = kHistThreads / kWave;
+        if (copies < 1)
+            copies = 1;
+        const size_t lds = (size_t)copies * np * per_pass;
+        if (kd.bytes == 4) {
+            OrderMap<uint32_t> om{(uint32_t)kd.flip, (uint32_t)kd.neg};
+            hipLaunchKernelGGL((radix_histogram_kernel<4, kHistThreads>), dim3(grid), dim3(kHistThreads), lds, s,
+                               reinterpret_cast<const uint32_t*>(keys), n, om, bits, p0, np, copies, h);
+        } else {
+            OrderMap<uint64_t> om{kd.flip, kd.neg};
+            hipLaunchKernelGGL((radix_histogram_kernel<8, kHistThreads>), dim3(grid), dim3(kHistThreads), lds, s,
+                               reinterpret_cast<const uint64_t*>(keys), n, om, bits, p0, np, copies, h);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_radix_scan(const uint64_t* hist, uint64_t* bases, int bits, int passes, hipStream_t s)
+{
+    hipLaunchKernelGGL((radix_scan_kernel<256>), dim3(passes), dim3(256), 0, s, hist, bases, 1 << bits);
+    return hipGetLastError();
+}
+
+RadixShape radix_default_shape(int key_bytes, int val_bytes) { return radix_default_shape_c(key_bytes, val_bytes); }
+
+bool radix_pass_available(int key_bytes, int val_bytes, int bits, RadixShape sh, int status_bytes)
+{
+    if (key_bytes != 4 && key_bytes != 8)
+        return false;
+    if (val_bytes != 0 && val_bytes != 4 && val_bytes != 8)
+        return false;
+    if (bits < 4 || bits > 12 || (status_bytes != 4 && status_bytes != 8))
+        return false;
+    if (radix_lds_bytes(key_bytes, val_bytes, bits, sh.threads, sh.items) > kLdsLimit)
+        return false;
+    const RadixShape def = radix_default_shape_c(key_bytes, val_bytes);
+    if (sh.threads == def.threads && sh.items == def.items)
+        return true;
+    if (bits != 8)
+        return false;
+#define EVOSORT_MATCH_SHAPE(T, I)                 \
+    if (sh.threads == (T) && sh.items == (I))     \
+        return true;
+    EVOSORT_RADIX_ALT_SHAPES(EVOSORT_MATCH_SHAPE)
+#undef EVOSORT_MATCH_SHAPE
+    return false;
+}
+
+hipError_t launch_radix_pass(const KeyDesc& kd, int val_bytes, int bits, RadixShape shape, int status_bytes,
+                             const RadixPassArgs& a, uint32_t tiles, hipStream_t s)
+{
+    bool found = false;
+    hipError_t e = hipErrorInvalidValue;
+    if (kd.bytes == 4) {
+        if (val_bytes == 0)
+            e = radix_pass_dispatch_k4_v0(bits, shape, status_bytes, kd, a, tiles, s, &found);
+        else if (val_bytes == 4)
+            e = radix_pass_dispatch_k4_v4(bits, shape, status_bytes, kd, a, tiles, s, &found);
+        else
+            e = radix_pass_dispatch_k4_v8(bits, shape, status_bytes, kd, a, tiles, s, &found);
+    } else {
+        if (val_bytes == 0)
+            e = radix_pass_dispatch_k8_v0(bits, shape, status_bytes, kd, a, tiles, s, &found);
+        else if (val_bytes == 4)
+            e = radix_pass_dispatch_k8_v4(bits, shape, status_bytes, kd, a, tiles, s, &found);
+        else
+            e = radix_pass_dispatch_k8_v8(bits, shape, status_bytes, kd, a, tiles, s, &found);
+    }
+    if (!found)
+        return hipErrorInvalidValue;
+    return e;
+}
+
+// ------------------------------------------------------------------ misc ---
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(uint4* p, size_t n16)
+{
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride)
+        p[i] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(256) void fill_zero_bytes_kernel(unsigned char* p, size_t bytes)
+{
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < bytes; i += stride)
+        p[i] = 0;
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0)
+        return hipSuccess;
+    if ((bytes & 15) || (reinterpret_cast<uintptr_t>(p) & 15)) {
+        size_t grid = (bytes + 255) / 256;
+        if (grid > 8192)
+            grid = 8192;
+        hipLaunchKernelGGL(fill_zero_bytes_kernel, dim3((unsigned)grid), dim3(256), 0, s,
+                           reinterpret_cast<unsigned char*>(p), bytes);
+        return hipGetLastError();
+    }
+    const size_t n16 = bytes / 16;
+    size_t grid = (n16 + 255) / 256;
+    if (grid > 8192)
+        grid = 8192;
+    if (grid < 1)
+        grid = 1;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)grid), dim3(256), 0, s, reinterpret_cast<uint4*>(p), n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0 || dst == src)
+        return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+}
+
+}  // namespace evosort

@@ -1,0 +1,30 @@
+// One-workgroup sort of small arrays (host-visible part).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+namespace evosort {
+
+// Largest n the one-workgroup sort takes: the records of the whole array must
+// fit in LDS (8 bytes per 4-byte key: 128 KB; 12 bytes per 8-byte key: 96 KB).
+constexpr int kSmallCapacity4 = 16384;
+constexpr int kSmallCapacity8 = 8192;
+
+enum SmallMode : int { SMALL_MODE_KEYS = 0, SMALL_MODE_PAIRS = 1, SMALL_MODE_ARGSORT = 2 };
+
+struct SmallSortArgs {
+    const void* keys_in;
+    void* keys_out;       // unused for argsort
+    const void* vals_in;  // pairs only
+    void* vals_out;       // values (pairs) or indices (argsort)
+    int64_t n;
+    int mode;
+};
+
+int64_t small_sort_capacity(int key_bytes, int val_bytes);
+hipError_t launch_small_sort(const KeyDesc& kd, int val_bytes, const SmallSortArgs& a, hipStream_t s);
+
+}  // namespace evosort

@@ -26,7 +26,7 @@ ALL_DTYPES = [np.int32, np.int64, np.uint32, np.float32, np.float64]
 # Key order
 # --------------------------------------------------------------------------
 def test_sign_flip_matches_paper_masks():
-    """Signed keys: order key = value XOR sign mask (Sec. 4.3 masks), from a golden table."""
+    """Signed keys: order key = value XOR sign mask (masks of Sec. 4, Algorithms 4 and 5), from a golden table."""
     rows = read_golden("int_sign_flip.txt")
     assert rows
     for dt, val, mapped in rows:
@@ -192,7 +192,7 @@ def test_histogram_uint32_equals_bincount(bits):
 
 
 def test_histogram_int32_equals_xor_masked_uint32():
-    """The paper's XOR-0x80000000 form (Sec. 4.3) against the oracle's own offset form."""
+    """The paper's XOR-0x80000000 form (Sec. 4, Algorithm 4) against the oracle's own offset form."""
     x = workloads.uniform(np.int32, 40_000, 3)
     flipped = x.view(np.uint32) ^ np.uint32(0x80000000)
     assert np.array_equal(oracle.digit_histogram(x, 8), oracle.digit_histogram(flipped, 8))
@@ -261,7 +261,7 @@ def test_merge_round_merges_pairs(run):
 @pytest.mark.parametrize("dt", ALL_DTYPES)
 @pytest.mark.parametrize("chunk", [2, 3, 17, 195, 629, 2048])
 def test_bottom_up_schedule_reaches_the_stable_sort(dt, chunk):
-    """Sec. 4.3 mergesort schedule: insertion chunks, then runs doubling from the chunk size."""
+    """Mergesort schedule of Sec. 4, Algorithm 3: insertion chunks, then runs doubling from the chunk size."""
     g = np.random.default_rng(chunk)
     n = 6007
     keys = workloads.uniform(dt, n, chunk)

@@ -5,7 +5,7 @@ imports neither the GPU library nor the oracle.  Every generator is a pure
 function of (size, seed) built on numpy's PCG64 generator.
 
 Distributions (the paper's own inputs are synthetic integer arrays drawn with a
-fixed seed, 42 by default, Sec. 5 and Sec. 7.5):
+fixed seed, 42 by default, Sec. 7.5 and the data availability statement):
 
 * ``uniform``        -- i.i.d. uniform over the full bit range of the dtype
                         (floats: uniform bit patterns, NaN patterns redrawn);
