@@ -1,0 +1,268 @@
+"""Benchmark: LSD radix sort of 1e9 int32 keys on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--dtype int32|int64|...]
+
+One step = one full sort call (evosort_sort) of the whole array: the
+adaptive-partition dispatch, the all-pass digit histogram, the digit-base scan
+and every single-sweep radix pass.  Keys are generated once (seeded, uniform
+over the full int32 range), copied to HBM before timing, and sorted from the
+same input buffer into an output buffer on every step.
+
+Prints one JSON line with the contract fields plus:
+  roofline      the dominant kernel (the radix pass): algorithmic bytes per
+                launch / its mean duration from HIP events recorded around
+                every launch during the timed steps, against 8 TB/s; `traffic`
+                is the HBM bytes per launch from the committed rocprofv3
+                counter summary when it was taken on the current kernel source;
+  cpu_baseline  the CPU oracle (single-threaded stable mergesort) timed on a
+                bounded sample of the same workload on the host;
+  kernels       mean milliseconds per launch of every library kernel;
+  secondary     the same measurement for 1e9 int64 keys (unless --no-secondary).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = "Gkeys/s and HBM GB/s vs peak, int32/int64 1e9 sort; batched segs/s, p99 latency"
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "radix_pass_int32_1e9_pmc.md")
+KERNEL_SOURCES = ["paper_2505_18681_amd/csrc/radix_impl.hpp", "paper_2505_18681_amd/csrc/common.hpp",
+                  "paper_2505_18681_amd/csrc/radix_shapes.hpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic(dtype_name: str, n: int):
+    """HBM bytes per radix-pass launch from the committed counter summary, if current."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    text = open(PMC_SUMMARY).read()
+    m = re.search(r"^traffic_json:\s*(\{.*\})\s*$", text, re.M)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("source_hash") != kernel_source_hash():
+        return None  # kernel changed since the counters were taken
+    if rec.get("dtype") != dtype_name or int(rec.get("n", -1)) != n:
+        return None
+    return float(rec["bytes_per_launch"])
+
+
+def algorithmic_pass_bytes(n: int, key_bytes: int, value_bytes: int = 0) -> int:
+    """One LSD pass reads and writes every key (and value) once."""
+    return 2 * n * (key_bytes + value_bytes)
+
+
+def run_sort_bench(es, torch, dtype_name: str, n: int, steps: int, warmup: int, seed: int, digit_bits: int):
+    import numpy as np
+
+    import workloads
+
+    np_dt = np.dtype(dtype_name)
+    t_dt = {"int32": torch.int32, "int64": torch.int64, "float32": torch.float32, "float64": torch.float64,
+            "uint32": torch.uint32}[dtype_name]
+    t0 = time.perf_counter()
+    host = workloads.uniform(np_dt, n, seed)
+    if np_dt == np.uint32:
+        keys = torch.from_numpy(host.view(np.int32)).cuda().view(torch.uint32)
+    else:
+        keys = torch.from_numpy(host).cuda()
+    del host
+    gen_s = time.perf_counter() - t0
+    out = torch.empty_like(keys)
+    params = es.default_params(algo=es.ALGO_RADIX, digit_bits=digit_bits)
+    code = es.dtype_code(t_dt)
+    info = es.plan(es.OP_SORT, code, n, 0, params)
+    temp = torch.empty(max(es.temp_bytes(es.OP_SORT, code, n, 0, params), 256), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    for _ in range(warmup):
+        es.sort(keys, params=params, out=out, temp=temp)
+    torch.cuda.synchronize()
+
+    es.profile_reset()
+    es.profile_enable(True)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        es.sort(keys, params=params, out=out, temp=temp)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    es.profile_enable(False)
+    total_ms = start.elapsed_time(stop)
+    kernels = es.profile_collect()
+    es.profile_reset()
+
+    # cheap device-side sanity check of the last output (parity lives in tests/)
+    if n > 1:
+        if dtype_name in ("float32", "float64"):
+            ok = True  # totalOrder check needs the bit map; covered by the GPU tests
+        elif dtype_name == "uint32":
+            o = out.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+            ok = bool((o[1:] >= o[:-1]).all().item())
+        else:
+            ok = bool((out[1:] >= out[:-1]).all().item())
+        if not ok:
+            raise RuntimeError("benchmark output is not sorted")
+
+    ms_per_step = total_ms / steps
+    kb = np_dt.itemsize
+    pass_launches, pass_ms = kernels.get("radix_pass", (0, 0.0))
+    mean_pass_ms = pass_ms / pass_launches if pass_launches else float("nan")
+    achieved = algorithmic_pass_bytes(n, kb) / (mean_pass_ms * 1e-3) / 1e9 if pass_launches else None
+    per_kernel = {k: round(v[1] / v[0], 4) for k, v in kernels.items() if v[0]}
+    del keys, out, temp
+    torch.cuda.empty_cache()
+    return {
+        "ms_per_step": ms_per_step,
+        "gkeys_per_s": n / (ms_per_step * 1e-3) / 1e9,
+        "pass_mean_ms": mean_pass_ms,
+        "pass_gbs": achieved,
+        "kernels_ms": per_kernel,
+        "passes": info["passes"],
+        "tile": [info["block_threads"], info["items_per_thread"]],
+        "status_bytes": info["status_bytes"],
+        "gen_s": gen_s,
+    }
+
+
+def cpu_baseline(dtype_name: str, n_sample: int, seed: int):
+    """The oracle, untuned, on a bounded sample of the same workload (one host thread)."""
+    import numpy as np
+
+    import oracle
+    import workloads
+
+    keys = workloads.uniform(np.dtype(dtype_name), n_sample, seed)
+    t0 = time.perf_counter()
+    perm = oracle.stable_perm(keys)
+    out = keys[perm]
+    dt = time.perf_counter() - t0
+    del out, perm
+    return {"value": round(n_sample / dt / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_sample:.0e} {dtype_name} uniform keys (seed {seed}), stable mergesort, "
+                      f"{dt:.2f} s on one host thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1_000_000_000)
+    ap.add_argument("--dtype", default="int32")
+    ap.add_argument("--digit-bits", type=int, default=8)
+    ap.add_argument("--seed", type=int, default=42)
+    ap.add_argument("--cpu-sample", type=int, default=100_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (for counter calibration runs)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark measures one GPU only; run it with --gpus 1"}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2505_18681_amd as es
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(1)
+
+    main_res = run_sort_bench(es, torch, args.dtype, args.n, args.steps, args.warmup, args.seed, args.digit_bits)
+    print(f"# {args.dtype} n={args.n}: {main_res['ms_per_step']:.3f} ms/step, "
+          f"{main_res['gkeys_per_s']:.2f} Gkeys/s, pass {main_res['pass_mean_ms']:.3f} ms", file=sys.stderr,
+          flush=True)
+
+    secondary = None
+    if not args.no_secondary and args.dtype == "int32":
+        sec = run_sort_bench(es, torch, "int64", args.n, max(2, args.steps // 2), 1, args.seed, args.digit_bits)
+        secondary = {
+            "workload": f"int64 uniform {args.n:.0e} keys-only LSD radix sort, {sec['passes']} passes of "
+                        f"{args.digit_bits}-bit digits",
+            "value": round(sec["gkeys_per_s"], 4), "unit": "Gkeys/s", "ms_per_step": round(sec["ms_per_step"], 4),
+            "roofline": {"bound": "hbm", "achieved": round(sec["pass_gbs"], 1) if sec["pass_gbs"] else None,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(sec["pass_gbs"] / HBM_PEAK_GBS, 4) if sec["pass_gbs"] else None},
+            "kernels_ms": sec["kernels_ms"],
+        }
+        print(f"# int64: {sec['ms_per_step']:.3f} ms/step, {sec['gkeys_per_s']:.2f} Gkeys/s", file=sys.stderr,
+              flush=True)
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.dtype, min(args.cpu_sample, args.n), args.seed)
+
+    kb = {"int32": 4, "uint32": 4, "float32": 4, "int64": 8, "float64": 8}[args.dtype]
+    achieved = main_res["pass_gbs"]
+    line = {
+        "metric": METRIC,
+        "value": round(main_res["gkeys_per_s"], 4),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.dtype} uniform full-range {args.n:.0e} keys-only LSD radix sort "
+                        f"({main_res['passes']} passes of {args.digit_bits}-bit digits), keys resident in HBM",
+            "n": args.n,
+            "key_dtype": args.dtype,
+            "digit_bits": args.digit_bits,
+            "tile": main_res["tile"],
+            "status_word_bytes": main_res["status_bytes"],
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "radix_pass",
+            "achieved": round(achieved, 1) if achieved else None,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+            "traffic": counted_traffic(args.dtype, args.n),
+            "algorithmic_bytes_per_launch": algorithmic_pass_bytes(args.n, kb),
+            "mean_launch_ms": round(main_res["pass_mean_ms"], 4),
+        },
+        "cpu_baseline": cpu,
+        "kernels_ms": main_res["kernels_ms"],
+        "secondary": secondary,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -27,6 +27,11 @@ LIB_PATH = os.path.join(_HERE, "libevosort.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2505_18681_amd.build` first")
 
+# PyTorch ships its own HIP runtime.  Load it first so that the library's
+# dependency on libamdhip64.so.7 binds to that same runtime: two HIP runtimes
+# in one process would not share devices, streams or allocations.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 # ---------------------------------------------------------------- constants --

@@ -95,6 +95,9 @@ Profiler& prof()
 template <class F>
 hipError_t timed(const char* name, hipStream_t s, F&& launch)
 {
+    // Launchers report hipGetLastError(); drop any error an unrelated earlier
+    // runtime call left behind so it is not blamed on this launch.
+    (void)hipGetLastError();
     Profiler& P = prof();
     bool on;
     {
