@@ -69,7 +69,8 @@ def algorithmic_pass_bytes(n: int, key_bytes: int, value_bytes: int = 0) -> int:
     return 2 * n * (key_bytes + value_bytes)
 
 
-def run_sort_bench(es, torch, dtype_name: str, n: int, steps: int, warmup: int, seed: int, digit_bits: int):
+def run_sort_bench(es, torch, dtype_name: str, n: int, steps: int, warmup: int, seed: int, digit_bits: int,
+                   tile=None, algo: str = "radix"):
     import numpy as np
 
     import workloads
@@ -86,7 +87,10 @@ def run_sort_bench(es, torch, dtype_name: str, n: int, steps: int, warmup: int, 
     del host
     gen_s = time.perf_counter() - t0
     out = torch.empty_like(keys)
-    params = es.default_params(algo=es.ALGO_RADIX, digit_bits=digit_bits)
+    params = es.default_params(algo=es.ALGO_RADIX if algo == "radix" else es.ALGO_MERGE, digit_bits=digit_bits,
+                               fallback_threshold=0)
+    if tile:
+        params.block_threads, params.items_per_thread = tile
     code = es.dtype_code(t_dt)
     info = es.plan(es.OP_SORT, code, n, 0, params)
     temp = torch.empty(max(es.temp_bytes(es.OP_SORT, code, n, 0, params), 256), dtype=torch.uint8, device="cuda")
@@ -169,6 +173,8 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000_000)
     ap.add_argument("--dtype", default="int32")
     ap.add_argument("--digit-bits", type=int, default=8)
+    ap.add_argument("--tile", default=None, help="radix tile shape THREADS,ITEMS (default: library default)")
+    ap.add_argument("--algo", choices=["radix", "merge"], default="radix")
     ap.add_argument("--seed", type=int, default=42)
     ap.add_argument("--cpu-sample", type=int, default=100_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -190,14 +196,17 @@ def main():
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         sys.exit(1)
 
-    main_res = run_sort_bench(es, torch, args.dtype, args.n, args.steps, args.warmup, args.seed, args.digit_bits)
+    tile = tuple(int(x) for x in args.tile.split(",")) if args.tile else None
+    main_res = run_sort_bench(es, torch, args.dtype, args.n, args.steps, args.warmup, args.seed, args.digit_bits,
+                              tile, args.algo)
     print(f"# {args.dtype} n={args.n}: {main_res['ms_per_step']:.3f} ms/step, "
           f"{main_res['gkeys_per_s']:.2f} Gkeys/s, pass {main_res['pass_mean_ms']:.3f} ms", file=sys.stderr,
           flush=True)
 
     secondary = None
-    if not args.no_secondary and args.dtype == "int32":
-        sec = run_sort_bench(es, torch, "int64", args.n, max(2, args.steps // 2), 1, args.seed, args.digit_bits)
+    if not args.no_secondary and args.dtype == "int32" and args.algo == "radix":
+        sec = run_sort_bench(es, torch, "int64", args.n, max(2, args.steps // 2), 1, args.seed, args.digit_bits,
+                             None, args.algo)
         secondary = {
             "workload": f"int64 uniform {args.n:.0e} keys-only LSD radix sort, {sec['passes']} passes of "
                         f"{args.digit_bits}-bit digits",

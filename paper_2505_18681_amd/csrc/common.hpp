@@ -62,6 +62,51 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 
 __device__ __forceinline__ uint64_t ballot(bool pred) { return __builtin_amdgcn_ballot_w64(pred); }
 
+// acc & ~(m ^ sel): keep the lanes of `acc` whose ballot bit in `m` equals
+// this lane's bit (sel = all ones or zero), as one 3-input bit operation.
+// The truth table is indexed by (acc, m, sel) as a 3-bit number; it is true at
+// (1,0,0) and (1,1,1).
+__device__ __forceinline__ uint32_t keep_equal_bits(uint32_t acc, uint32_t m, uint32_t sel)
+{
+    return __builtin_amdgcn_bitop3_b32(acc, m, sel, 0x90);
+}
+
+// Returns x unchanged, but only once y has been computed: an empty asm that
+// claims to read y and rewrite x, to order otherwise independent work.
+__device__ __forceinline__ uint32_t after(uint32_t x, uint32_t y)
+{
+    asm volatile("" : "+v"(x) : "v"(y));
+    return x;
+}
+
+// All ones if bit b of x is set, else zero (a sign-extended 1-bit field).
+// Written as one instruction so that the compiler tests this value for the
+// ballot instead of re-deriving the bit with a shift and a compare.
+template <int B>
+__device__ __forceinline__ uint32_t bit_mask_of_c(uint32_t x)
+{
+    uint32_t r;
+    asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(r) : "v"(x), "i"(B));
+    return r;
+}
+__device__ __forceinline__ uint32_t bit_mask_of(uint32_t x, int b)
+{
+    switch (b) {
+    case 0: return bit_mask_of_c<0>(x);
+    case 1: return bit_mask_of_c<1>(x);
+    case 2: return bit_mask_of_c<2>(x);
+    case 3: return bit_mask_of_c<3>(x);
+    case 4: return bit_mask_of_c<4>(x);
+    case 5: return bit_mask_of_c<5>(x);
+    case 6: return bit_mask_of_c<6>(x);
+    case 7: return bit_mask_of_c<7>(x);
+    case 8: return bit_mask_of_c<8>(x);
+    case 9: return bit_mask_of_c<9>(x);
+    case 10: return bit_mask_of_c<10>(x);
+    default: return bit_mask_of_c<11>(x);
+    }
+}
+
 __device__ __forceinline__ int lane_id() { return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
 // Agent-scope relaxed atomics for words that other workgroups (on any XCD)

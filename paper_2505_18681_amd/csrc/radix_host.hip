@@ -74,7 +74,13 @@ hipError_t launch_radix_scan(const uint64_t* hist, uint64_t* bases, int bits, in
     return hipGetLastError();
 }
 
-RadixShape radix_default_shape(int key_bytes, int val_bytes) { return radix_default_shape_c(key_bytes, val_bytes); }
+RadixShape radix_default_shape(int key_bytes, int val_bytes, int bits)
+{
+    const RadixShape def = radix_default_shape_c(key_bytes, val_bytes);
+    if (radix_lds_bytes(key_bytes, val_bytes, bits, def.threads, def.items) <= kLdsLimit)
+        return def;
+    return kRadixFallbackShape;
+}
 
 bool radix_pass_available(int key_bytes, int val_bytes, int bits, RadixShape sh, int status_bytes)
 {
@@ -88,6 +94,8 @@ bool radix_pass_available(int key_bytes, int val_bytes, int bits, RadixShape sh,
         return false;
     const RadixShape def = radix_default_shape_c(key_bytes, val_bytes);
     if (sh.threads == def.threads && sh.items == def.items)
+        return true;
+    if (sh.threads == kRadixFallbackShape.threads && sh.items == kRadixFallbackShape.items)
         return true;
     if (bits != 8)
         return false;

@@ -49,13 +49,30 @@ __global__ __launch_bounds__(THREADS) void radix_histogram_kernel(const typename
     };
 
     constexpr int VEC = 16 / KB;  // keys per 16-byte load
+    constexpr int UNROLL = 4;     // 16-byte loads in flight per thread
     const int64_t stride = (int64_t)gridDim.x * THREADS;
     const int64_t gtid = (int64_t)blockIdx.x * THREADS + threadIdx.x;
     int64_t done = 0;
     if ((reinterpret_cast<uintptr_t>(keys) & 15) == 0) {
         const int64_t nvec = n / VEC;
         const uint4* kv = reinterpret_cast<const uint4*>(keys);
-        for (int64_t v = gtid; v < nvec; v += stride) {
+        int64_t v = gtid;
+        // Issue UNROLL independent loads before counting any of them.
+        for (; v + (UNROLL - 1) * stride < nvec; v += UNROLL * stride) {
+            uint4 w[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u)
+                w[u] = kv[v + u * stride];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                U k[VEC];
+                __builtin_memcpy(k, &w[u], 16);
+#pragma unroll
+                for (int j = 0; j < VEC; ++j)
+                    count(k[j]);
+            }
+        }
+        for (; v < nvec; v += stride) {
             uint4 w = kv[v];
             U k[VEC];
             __builtin_memcpy(k, &w, 16);
@@ -129,6 +146,71 @@ struct Status<uint64_t> {
 constexpr uint32_t kFlagAggregate = 1;  // count of this tile only
 constexpr uint32_t kFlagInclusive = 2;  // count of this tile and every tile before it
 
+// Number of predecessor look-back words read at once.  Each agent-scope read
+// crosses to memory (the XCDs' L2s are not coherent with each other), so the
+// walk reads several predecessors per round trip.
+constexpr int kLookBackWindow = 4;
+
+// Sum of digit b's counts over tiles [0, tile): walk back from tile - 1,
+// reading kLookBackWindow words per round trip, adding aggregates until an
+// inclusive word ends the walk.  An unpublished word is polled (bounded by
+// spin_limit; running out sets *error_word and returns what was summed).
+// Tile 0 always publishes an inclusive word, so the walk never passes it;
+// window slots before tile 0 re-read tile 0's word (in bounds, never used
+// past it).
+template <typename ST, int BINS>
+__device__ __forceinline__ uint64_t look_back(const ST* status, uint32_t tile, int b, uint32_t spin_limit,
+                                              uint32_t* error_word)
+{
+    constexpr int W = kLookBackWindow;
+    uint64_t excl = 0;
+    int32_t t = (int32_t)tile - 1;
+    uint32_t spins = 0;
+    for (;;) {
+        ST s[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const int32_t tt = t - w > 0 ? t - w : 0;
+            s[w] = load_agent(&status[(size_t)(uint32_t)tt * BINS + b]);
+        }
+        int stop = W;  // window slot to wait on; W: none
+        bool done = false;
+#pragma unroll
+        for (int w = W - 1; w >= 0; --w) {
+            // scanning from the far end keeps the nearest unpublished slot
+            const uint32_t flag = (uint32_t)(s[w] >> Status<ST>::kShift);
+            if (flag == 0)
+                stop = w;
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            if (!done && w < stop) {
+                excl += (uint64_t)(s[w] & Status<ST>::kMask);
+                done = (uint32_t)(s[w] >> Status<ST>::kShift) == kFlagInclusive;
+            }
+        }
+        if (done)
+            return excl;
+        if (stop == W) {
+            t -= W;
+            continue;
+        }
+        t -= stop;
+        ST x;
+        while (((x = load_agent(&status[(size_t)(uint32_t)t * BINS + b])) >> Status<ST>::kShift) == 0) {
+            if (++spins > spin_limit) {
+                atomicOr(error_word, 1u);
+                return excl;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        excl += (uint64_t)(x & Status<ST>::kMask);
+        if ((uint32_t)(x >> Status<ST>::kShift) == kFlagInclusive)
+            return excl;
+        --t;
+    }
+}
+
 // ------------------------------------------------------------------------
 // One single-sweep LSD pass
 // ------------------------------------------------------------------------
@@ -137,99 +219,150 @@ constexpr uint32_t kFlagInclusive = 2;  // count of this tile and every tile bef
 // and its item i is lane-striped: key w*64*ITEMS + i*64 + lane.  Processing
 // items in order i = 0, 1, ... and lanes in order inside an item therefore
 // visits the tile's keys in input order, which is what makes the rank stable.
-template <int KB, int VB, int BITS, int THREADS, int ITEMS, typename ST>
-__global__ __launch_bounds__(THREADS) void radix_pass_kernel(RadixPassArgs a, OrderMap<typename KeyWord<KB>::U> om)
+
+// LDS of one pass workgroup.  The per-wave digit counters and the output
+// staging area are never live at the same time, so they share storage.
+template <int KB, int VB, int BITS, int THREADS, int ITEMS>
+struct PassLds {
+    static constexpr int BINS = 1 << BITS;
+    static constexpr int WAVES = THREADS / kWave;
+    static constexpr int TILE = THREADS * ITEMS;
+    // counters [WAVES][BINS] uint32, then (digits up to 11 bits) lane
+    // buckets [WAVES][BINS] uint64
+    static constexpr bool kBuckets = BITS <= 11;
+    static constexpr size_t BUCKET_OFFSET = ((size_t)WAVES * BINS * 4 + 15) & ~(size_t)15;
+    static constexpr size_t HIST_BYTES = BUCKET_OFFSET + (kBuckets ? (size_t)WAVES * BINS * 8 : 0);
+    static constexpr size_t STAGE_BYTES = (size_t)TILE * KB + (size_t)(VB ? TILE * VB : 0);
+    static constexpr size_t UNION_BYTES = HIST_BYTES > STAGE_BYTES ? HIST_BYTES : STAGE_BYTES;
+    __attribute__((aligned(16))) unsigned char uni[UNION_BYTES];
+    int64_t gofs[BINS];  // output slot of tile position 0, per digit (32-bit values while n < 2^30)
+    uint32_t wtot[WAVES];
+    uint32_t next[2];  // tickets, double-buffered by loop parity
+};
+
+// Everything a workgroup does for one tile after it has its tile number.
+// FULL: the tile holds TILE keys (every tile but possibly the last), so no
+// per-item validity is tracked.
+template <bool FULL, int KB, int VB, int BITS, int THREADS, int ITEMS, typename ST>
+__device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap<typename KeyWord<KB>::U>& om,
+                                          PassLds<KB, VB, BITS, THREADS, ITEMS>& L, uint32_t tile, int64_t tile_start,
+                                          uint32_t nvalid)
 {
     using U = typename KeyWord<KB>::U;
     using V = typename ValWord<VB>::T;
+    using Lds = PassLds<KB, VB, BITS, THREADS, ITEMS>;
     constexpr int BINS = 1 << BITS;
     constexpr int WAVES = THREADS / kWave;
     constexpr int TILE = THREADS * ITEMS;
     constexpr int WAVE_KEYS = kWave * ITEMS;
     constexpr int BPT = (BINS + THREADS - 1) / THREADS;  // bins per thread
-    constexpr size_t HIST_BYTES = (size_t)WAVES * BINS * 4;
-    constexpr size_t STAGE_BYTES = (size_t)TILE * KB + (size_t)(VB ? TILE * VB : 0);
-    constexpr size_t UNION_BYTES = HIST_BYTES > STAGE_BYTES ? HIST_BYTES : STAGE_BYTES;
-    static_assert(WAVE_KEYS < 65536, "rank field is 16 bits");
-    static_assert(BINS <= 4096, "digit field is 12 bits");
+    // With 32-bit look-back words n < 2^30, so output slots fit in 32 bits.
+    constexpr bool kOff32 = sizeof(ST) == 4;
 
-    // The per-wave digit counters and the output staging area are never live
-    // at the same time, so they share LDS.
-    __shared__ __attribute__((aligned(16))) unsigned char s_union[UNION_BYTES];
-    __shared__ int64_t s_gofs[BINS];  // output slot of tile position 0 for each digit
-    __shared__ uint32_t s_wtot[WAVES];
-    __shared__ uint32_t s_tile;
-
-    uint32_t* s_whist = reinterpret_cast<uint32_t*>(s_union);  // [WAVES][BINS]
-    U* s_keys = reinterpret_cast<U*>(s_union);
-    V* s_vals = reinterpret_cast<V*>(s_union + (size_t)TILE * KB);
-
-    const U* __restrict__ keys_in = reinterpret_cast<const U*>(a.keys_in);
-    U* __restrict__ keys_out = reinterpret_cast<U*>(a.keys_out);
+    uint32_t* s_whist = reinterpret_cast<uint32_t*>(L.uni);  // [WAVES][BINS]
+    U* s_keys = reinterpret_cast<U*>(L.uni);
+    V* s_vals = reinterpret_cast<V*>(L.uni + (size_t)TILE * KB);
     ST* status = reinterpret_cast<ST*>(a.status);
 
-    // Tiles are handed out in launch order, so a tile only ever waits on tiles
-    // whose workgroups are already running.
-    if (threadIdx.x == 0)
-        s_tile = atomicAdd(a.tile_counter, 1u);
-    for (int i = threadIdx.x; i < WAVES * BINS; i += THREADS)
-        s_whist[i] = 0;
-    __syncthreads();
-
-    const uint32_t tile = s_tile;
-    if (tile >= a.tiles)
-        return;  // uniform across the workgroup: cannot happen with a zeroed counter
-    const int64_t tile_start = (int64_t)tile * TILE;
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
-    const int64_t my0 = tile_start + (int64_t)w * WAVE_KEYS + lane;
-    const bool full = tile_start + TILE <= a.n;
+    // Offsets inside the tile are 32-bit; only the tile base is 64-bit.
+    const uint32_t off0 = (uint32_t)(w * WAVE_KEYS + lane);
+    const U* __restrict__ tile_keys = reinterpret_cast<const U*>(a.keys_in) + tile_start;
+    auto item_valid = [&](int i) { return FULL || off0 + (uint32_t)(i * kWave) < nvalid; };
 
     // ---- load ----------------------------------------------------------
+    // Past the end of the last tile the load is clamped to the last key (in
+    // bounds, no branch); such items are excluded from the rank below.
     U k[ITEMS];
     V v[VB ? ITEMS : 1];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const int64_t idx = my0 + (int64_t)i * kWave;
-        k[i] = (full || idx < a.n) ? keys_in[idx] : (U)0;
+        const uint32_t off = off0 + (uint32_t)(i * kWave);
+        k[i] = tile_keys[FULL ? off : (off < nvalid ? off : nvalid - 1)];
     }
     if constexpr (VB != 0) {
-        const V* __restrict__ vals_in = reinterpret_cast<const V*>(a.vals_in);
+        const V* __restrict__ tile_vals = reinterpret_cast<const V*>(a.vals_in) + tile_start;
+        const bool iota = (a.flags & RADIX_FLAG_IOTA) != 0;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const int64_t idx = my0 + (int64_t)i * kWave;
-            if (a.flags & RADIX_FLAG_IOTA)
-                v[i] = (V)idx;
+            const uint32_t off = off0 + (uint32_t)(i * kWave);
+            if (iota)
+                v[i] = (V)(tile_start + off);
             else
-                v[i] = (full || idx < a.n) ? vals_in[idx] : (V)0;
+                v[i] = tile_vals[FULL ? off : (off < nvalid ? off : nvalid - 1)];
         }
     }
 
+    // Zero the wave counters and buckets while the loads are in flight (the
+    // previous tile's write-out finished reading this storage at the barrier
+    // that ended it).
+    for (int i = threadIdx.x; i < WAVES * BINS; i += THREADS)
+        s_whist[i] = 0;
+    if constexpr (Lds::kBuckets) {
+        uint64_t* s_bkt = reinterpret_cast<uint64_t*>(L.uni + Lds::BUCKET_OFFSET);
+        for (int i = threadIdx.x; i < WAVES * BINS; i += THREADS)
+            s_bkt[i] = 0;
+    }
+    __syncthreads();
+
     // ---- stable rank inside each wave ------------------------------------
-    // For item i, the lanes holding the same digit are found with one ballot
-    // per digit bit; the lowest such lane bumps the wave's counter for that
-    // digit after all of them read it.  rk = digit << 16 | rank within wave.
-    uint32_t rk[ITEMS];
+    // Items are visited in order.  For item i every valid lane ORs its lane
+    // bit into the wave's 64-bit bucket of its digit, then reads the bucket
+    // back: the bits are exactly the lanes of this item holding the same
+    // digit (OR is order-independent, and one wave's LDS instructions run in
+    // program order).  Each lane also reads the wave's running count for its
+    // digit; the lowest lane of the group then clears the bucket and adds the
+    // group size to the count.
+    //   rk = digit << 16 | rank of the key among the wave's equal digits
     uint32_t* wh = s_whist + w * BINS;
+    uint32_t rk[ITEMS];
+    if constexpr (Lds::kBuckets) {
+        uint64_t* bkt = reinterpret_cast<uint64_t*>(L.uni + Lds::BUCKET_OFFSET) + w * BINS;
+        const uint64_t my_bit = 1ull << lane;
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const bool valid = full || (my0 + (int64_t)i * kWave < a.n);
-        const uint32_t d = (uint32_t)((om.to_order(k[i]) >> a.shift) & (U)(BINS - 1));
-        uint64_t peers = ballot(valid);
-#pragma unroll
-        for (int b = 0; b < BITS; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = ballot(bit);
-            peers &= bit ? m : ~m;
-        }
-        const uint32_t below = lanes_below(peers);
-        uint32_t old = 0;
-        if (valid) {
-            old = wh[d];
-            if (below == 0)
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t d = (uint32_t)((om.to_order(k[i]) >> a.shift) & (U)(BINS - 1));
+            const bool valid = item_valid(i);
+            if (FULL || valid)
+                atomicOr(reinterpret_cast<unsigned long long*>(&bkt[d]), (unsigned long long)my_bit);
+            const uint64_t peers = bkt[d];
+            const uint32_t old = wh[d];
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+            if ((FULL || valid) && below == 0) {
+                bkt[d] = 0;
                 wh[d] = old + (uint32_t)__popcll(peers);
+            }
+            rk[i] = (d << 16) | (old + below);
         }
-        rk[i] = (d << 16) | (old + below);
+    } else {
+        // Wide digits (the buckets would not fit in LDS): the same peer mask
+        // from one ballot per digit bit; a lane keeps the lanes whose bit
+        // equals its own (peers &= ~(ballot ^ sel), sel = all ones when set).
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            uint32_t d = (uint32_t)((om.to_order(k[i]) >> a.shift) & (U)(BINS - 1));
+            // Item i's ballots start after item i-1's result: otherwise the
+            // compiler hoists every item's 64-bit ballots and spills them.
+            if (i > 0)
+                d = after(d, rk[i - 1]);
+            const bool valid = item_valid(i);
+            const uint64_t vmask = FULL ? ~0ull : ballot(valid);
+            uint32_t plo = (uint32_t)vmask, phi = (uint32_t)(vmask >> 32);
+#pragma unroll
+            for (int b = 0; b < BITS; ++b) {
+                const uint32_t sel = bit_mask_of(d, b);
+                const uint64_t m = ballot(sel != 0);
+                plo = keep_equal_bits(plo, (uint32_t)m, sel);
+                phi = keep_equal_bits(phi, (uint32_t)(m >> 32), sel);
+            }
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
+            const uint32_t old = wh[d];
+            if ((FULL || valid) && below == 0)
+                wh[d] = old + (uint32_t)(__builtin_popcount(plo) + __builtin_popcount(phi));
+            rk[i] = (d << 16) | (old + below);
+        }
     }
     __syncthreads();
 
@@ -259,7 +392,7 @@ __global__ __launch_bounds__(THREADS) void radix_pass_kernel(RadixPassArgs a, Or
         }
     }
     uint32_t tile_total;
-    const uint32_t first = block_exclusive_scan<THREADS>(tsum, s_wtot, &tile_total);
+    const uint32_t first = block_exclusive_scan<THREADS>(tsum, L.wtot, &tile_total);
     (void)tile_total;
 
     // Turn each wave's digit counts into the wave's first local position.
@@ -283,6 +416,23 @@ __global__ __launch_bounds__(THREADS) void radix_pass_kernel(RadixPassArgs a, Or
         }
     }
 
+    __syncthreads();  // every wave's first local positions are in LDS
+
+    // ---- local positions, then stage the tile in digit order ----------------
+    // Done before the look-back so that predecessors get more time to publish.
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+        rk[i] = item_valid(i) ? s_whist[w * BINS + (rk[i] >> 16)] + (rk[i] & 0xffffu) : 0xffffffffu;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        if (FULL || rk[i] != 0xffffffffu) {
+            s_keys[rk[i]] = k[i];
+            if constexpr (VB != 0)
+                s_vals[rk[i]] = v[i];
+        }
+    }
+
     // ---- decoupled look-back per digit -------------------------------------
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
@@ -291,69 +441,97 @@ __global__ __launch_bounds__(THREADS) void radix_pass_kernel(RadixPassArgs a, Or
             continue;
         uint64_t excl = 0;
         if (tile > 0) {
-            int64_t t = (int64_t)tile - 1;
-            uint32_t spins = 0;
-            while (true) {
-                const ST s = load_agent(&status[(size_t)t * BINS + b]);
-                const uint32_t flag = (uint32_t)(s >> Status<ST>::kShift);
-                if (flag == 0) {
-                    if (++spins > a.spin_limit) {
-                        atomicOr(a.error_word, 1u);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                excl += (uint64_t)(s & Status<ST>::kMask);
-                if (flag == kFlagInclusive || t == 0)
-                    break;
-                --t;
-            }
+            excl = look_back<ST, BINS>(status, tile, b, a.spin_limit, a.error_word);
             store_agent(&status[(size_t)tile * BINS + b],
                         (ST)(((ST)kFlagInclusive << Status<ST>::kShift) | (ST)(excl + cnt[j])));
         }
-        s_gofs[b] = (int64_t)(a.bases[b] + excl) - (int64_t)start[j];
+        const int64_t g = (int64_t)(a.bases[b] + excl) - (int64_t)start[j];
+        if constexpr (kOff32)
+            reinterpret_cast<int32_t*>(L.gofs)[b] = (int32_t)g;
+        else
+            L.gofs[b] = g;
     }
-    __syncthreads();
-
-    // ---- local positions, then stage the tile in digit order ----------------
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const bool valid = full || (my0 + (int64_t)i * kWave < a.n);
-        rk[i] = valid ? s_whist[w * BINS + (rk[i] >> 16)] + (rk[i] & 0xffffu) : 0xffffffffu;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        if (rk[i] != 0xffffffffu) {
-            s_keys[rk[i]] = k[i];
-            if constexpr (VB != 0)
-                s_vals[rk[i]] = v[i];
-        }
-    }
-    __syncthreads();
+    __syncthreads();  // staged keys and per-digit output slots are in LDS
 
     // ---- coalesced write-out: consecutive threads, consecutive positions ----
-    const int nvalid = full ? TILE : (int)(a.n - tile_start);
     const bool write_keys = !(a.flags & RADIX_FLAG_SKIP_KEYS);
+    U* __restrict__ keys_out = reinterpret_cast<U*>(a.keys_out);
     V* __restrict__ vals_out = reinterpret_cast<V*>(a.vals_out);
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const int p = i * THREADS + threadIdx.x;
-        if (p < nvalid) {
+        const uint32_t p = (uint32_t)(i * THREADS) + threadIdx.x;
+        if (FULL || p < nvalid) {
             const U key = s_keys[p];
             const uint32_t d = (uint32_t)((om.to_order(key) >> a.shift) & (U)(BINS - 1));
-            const int64_t dst = s_gofs[d] + p;
             // dst is in [0, n) whenever the histogram matches the keys; the
-            // check keeps a broken invariant from becoming a wild store.
-            if ((uint64_t)dst < (uint64_t)a.n) {
-                if (write_keys)
-                    keys_out[dst] = key;
-                if constexpr (VB != 0)
-                    vals_out[dst] = s_vals[p];
+            // bounds check keeps a broken invariant from becoming a wild store.
+            if constexpr (kOff32) {
+                const uint32_t dst = (uint32_t)(reinterpret_cast<const int32_t*>(L.gofs)[d] + (int32_t)p);
+                if (dst < (uint32_t)a.n) {
+                    if (write_keys)
+                        keys_out[dst] = key;
+                    if constexpr (VB != 0)
+                        vals_out[dst] = s_vals[p];
+                }
+            } else {
+                const int64_t dst = L.gofs[d] + p;
+                if ((uint64_t)dst < (uint64_t)a.n) {
+                    if (write_keys)
+                        keys_out[dst] = key;
+                    if constexpr (VB != 0)
+                        vals_out[dst] = s_vals[p];
+                }
             }
         }
     }
+}
+
+// Persistent: each workgroup loops over tiles taken from the ticket counter.
+// The next ticket is requested while the current tile is processed, so its
+// round trip overlaps useful work.  Tickets are handed out in increasing
+// order to running workgroups, so a tile only ever waits on tiles that are
+// being processed; every workgroup leaves once a ticket is past the last tile.
+template <int KB, int VB, int BITS, int THREADS, int ITEMS, typename ST>
+__global__ __launch_bounds__(THREADS) void radix_pass_kernel(RadixPassArgs a, OrderMap<typename KeyWord<KB>::U> om)
+{
+    using Lds = PassLds<KB, VB, BITS, THREADS, ITEMS>;
+    constexpr int TILE = THREADS * ITEMS;
+    static_assert(kWave * ITEMS < 65536, "rank field is 16 bits");
+    static_assert((1 << BITS) <= 4096, "digit field is 12 bits");
+    __shared__ Lds L;
+
+    if (threadIdx.x == 0)
+        L.next[0] = atomicAdd(a.tile_counter, 1u);
+    __syncthreads();
+    const uint32_t tile = L.next[0];
+    if (tile >= a.tiles)
+        return;  // uniform across the workgroup
+    const int64_t tile_start = (int64_t)tile * TILE;
+    const int64_t left = a.n - tile_start;
+    if (left >= TILE)
+        pass_tile<true, KB, VB, BITS, THREADS, ITEMS, ST>(a, om, L, tile, tile_start, (uint32_t)TILE);
+    else
+        pass_tile<false, KB, VB, BITS, THREADS, ITEMS, ST>(a, om, L, tile, tile_start, (uint32_t)left);
+}
+
+// Workgroups resident at once on the current device for a kernel (cached per
+// kernel; the library serves one device at a time per process thread, and
+// all MI355X devices have the same count).
+template <class K>
+int resident_groups(K kernel, int threads, int& cached)
+{
+    if (cached > 0)
+        return cached;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || cus <= 0 ||
+        per_cu <= 0) {
+        (void)hipGetLastError();
+        return 1024;  // any grid is correct; this only sizes the persistent launch
+    }
+    cached = cus * per_cu;
+    return cached;
 }
 
 template <int KB, int VB, int BITS, int THREADS, int ITEMS, typename ST>
@@ -361,8 +539,12 @@ hipError_t launch_radix_pass_t(const KeyDesc& kd, const RadixPassArgs& a, uint32
 {
     using U = typename KeyWord<KB>::U;
     OrderMap<U> om{(U)kd.flip, (U)kd.neg};
-    hipLaunchKernelGGL((radix_pass_kernel<KB, VB, BITS, THREADS, ITEMS, ST>), dim3(tiles), dim3(THREADS), 0, s, a,
-                       om);
+    auto kernel = radix_pass_kernel<KB, VB, BITS, THREADS, ITEMS, ST>;
+    static int cached = 0;  // one per instantiation
+    const uint32_t resident = (uint32_t)resident_groups(kernel, THREADS, cached);
+    const uint32_t grid = tiles;
+    (void)resident;
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(THREADS), 0, s, a, om);
     return hipGetLastError();
 }
 

@@ -3,9 +3,9 @@
 // -DEVOSORT_KB=<4|8> -DEVOSORT_VB=<0|4|8>, so the six pairs compile in
 // parallel.
 //
-// Compiled set: the default tile shape at every digit width 4..12, plus the
-// alternative tile shapes at digit width 8; each with 32-bit look-back words
-// (n < 2^30) and 64-bit ones.
+// Compiled set: the preferred and the fallback tile shape at every digit
+// width 4..12, plus the alternative tile shapes at digit width 8; each with
+// 32-bit look-back words (n < 2^30) and 64-bit ones.
 #include "radix_impl.hpp"
 #include "radix_shapes.hpp"
 
@@ -74,6 +74,8 @@ hipError_t by_shape(int bits, RadixShape sh, const KeyDesc& kd, const RadixPassA
     constexpr RadixShape def = radix_default_shape_c(EVOSORT_KB, EVOSORT_VB);
     if (sh.threads == def.threads && sh.items == def.items)
         return all_bits<def.threads, def.items, ST>(bits, kd, a, tiles, s, found);
+    if (sh.threads == kRadixFallbackShape.threads && sh.items == kRadixFallbackShape.items)
+        return all_bits<kRadixFallbackShape.threads, kRadixFallbackShape.items, ST>(bits, kd, a, tiles, s, found);
 #define EVOSORT_TRY_SHAPE(T, I)                                  \
     if (sh.threads == (T) && sh.items == (I))                    \
         return bits8<(T), (I), ST>(bits, kd, a, tiles, s, found);

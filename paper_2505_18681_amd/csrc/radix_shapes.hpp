@@ -12,23 +12,33 @@ namespace evosort {
 constexpr size_t kLdsLimit = 160 * 1024;
 
 // Static LDS of radix_pass_kernel<KB, VB, BITS, THREADS, ITEMS>: the union of
-// the per-wave digit counters and the staging area, the per-digit output
-// offsets, and a few words.
+// the per-wave digit counters and lane buckets with the staging area, the
+// per-digit output offsets, and a few words.
 constexpr size_t radix_lds_bytes(int kb, int vb, int bits, int threads, int items)
 {
     const size_t bins = (size_t)1 << bits;
-    const size_t hist = (size_t)(threads / 64) * bins * 4;
+    const size_t counters = (((size_t)(threads / 64) * bins * 4) + 15) & ~(size_t)15;
+    const size_t hist = counters + (bits <= 11 ? (size_t)(threads / 64) * bins * 8 : 0);
     const size_t stage = (size_t)threads * items * (size_t)(kb + vb);
     return (hist > stage ? hist : stage) + bins * 8 + (size_t)(threads / 64) * 4 + 16;
 }
 
-// Default shape per (key bytes, value bytes): compiled at every digit width.
+// Preferred shape per (key bytes, value bytes), measured at 8-bit digits on
+// 1e9-key arrays; compiled at every digit width (used where it fits in LDS).
 constexpr RadixShape radix_default_shape_c(int kb, int vb)
 {
-    return (kb + vb) >= 16 ? RadixShape{256, 12} : RadixShape{256, 16};
+    // keys-only int32 / int64; pairs with 4- and 8-byte values
+    if (kb == 4)
+        return vb == 4 ? RadixShape{512, 16} : RadixShape{512, 24};
+    return vb == 4 ? RadixShape{512, 24} : RadixShape{512, 16};
 }
 
+// Shape used when the preferred one does not fit at a digit width; compiled
+// at every digit width and fits in LDS at all of them.
+constexpr RadixShape kRadixFallbackShape{256, 8};
+
 // Alternative shapes, compiled at digit width 8 only (those that fit in LDS).
-#define EVOSORT_RADIX_ALT_SHAPES(X) X(256, 8) X(256, 12) X(256, 16) X(256, 24) X(256, 32) X(512, 8) X(512, 16)
+#define EVOSORT_RADIX_ALT_SHAPES(X) \
+    X(256, 8) X(256, 12) X(256, 16) X(256, 24) X(256, 32) X(256, 48) X(512, 8) X(512, 16) X(512, 24) X(512, 32) X(1024, 16)
 
 }  // namespace evosort
