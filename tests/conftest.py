@@ -22,6 +22,7 @@ if _MUTANT:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+    config.addinivalue_line("markers", "full_size: GPU parity at full benchmark sizes (minutes, >100 GB of HBM)")
 
 
 def golden_path(name: str) -> str:

@@ -1,0 +1,205 @@
+"""GPU parity at full benchmark sizes, in the launch configuration the benchmark times.
+
+At these sizes the oracle cannot sort the whole array in test time, so each
+result is checked by (1) outputs the oracle computes one by one -- the rank of
+sampled input elements under the stable sort -- and (2) properties that
+together equal "is the stable sort":
+
+* keys-only: ordered, and the same multiset (the argsort of the same input is
+  a permutation and gathers exactly the sorted keys);
+* argsort / key-value with the original index as value: the indices form a
+  permutation, gathering the input by them gives the sorted keys bit for bit,
+  and (order key, index) is strictly increasing (stability).
+
+Property checks run on the host with numpy over the copied-back arrays, or on
+the GPU with plain torch operations (never with this library).  Workloads:
+
+* 1e9 uniform int32 keys, default parameters (the benchmark's sort);
+* 1e8 int32 keys for each of the eight distributions of the sweep;
+* 1e10 uniform int32 keys (about 130 GB of HBM);
+* 2e9 float64 keys, N(0,1) with 1 % from {-inf, +inf, -0.0, +0.0}, sorted as
+  pairs with an int32 payload equal to the original index.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import require_gpu, to_dev, to_np
+
+pytestmark = [pytest.mark.gpu, pytest.mark.full_size]
+
+
+def _progress(msg):
+    sys.stderr.write(f"[full-size] {msg}\n")
+    sys.stderr.flush()
+
+
+def _check_ranks(keys, out, samples, seed):
+    """out[rank(i)] == keys[i] for sampled inputs i, rank from the oracle (O(n) each)."""
+    g = np.random.default_rng(seed)
+    bits = {4: np.uint32, 8: np.uint64}[keys.dtype.itemsize]
+    kb, ob = keys.view(bits), out.view(bits)
+    for i in g.integers(0, keys.size, samples):
+        r = oracle.rank_of(keys, int(i))
+        assert ob[r] == kb[i], f"sample {i}: rank {r}"
+
+
+def _check_argsort_exact(keys, sorted_keys, idx):
+    """idx is the stable sorting permutation of keys (sorted_keys computed by the GPU sort)."""
+    n = keys.size
+    seen = np.zeros(n, dtype=bool)
+    seen[idx] = True
+    assert seen.all(), "indices are not a permutation"
+    del seen
+    gathered = keys[idx]
+    bits = {4: np.uint32, 8: np.uint64}[keys.dtype.itemsize]
+    assert np.array_equal(gathered.view(bits), sorted_keys.view(bits)), "gather by indices differs from sorted keys"
+    del gathered
+    assert oracle.first_unsorted(sorted_keys) == -1, "sorted keys out of order"
+    same = sorted_keys.view(bits)[1:] == sorted_keys.view(bits)[:-1]
+    assert np.all(idx[1:][same] > idx[:-1][same]), "equal keys not in input order"
+
+
+@pytest.mark.timeout(900)
+def test_benchmark_sort_1e9_int32():
+    es = require_gpu()
+    import torch
+
+    n = 1_000_000_000
+    _progress("1e9 int32: generating")
+    keys = workloads.uniform(np.int32, n, workloads.DEFAULT_SEED)
+    d_keys = to_dev(keys)
+    info = es.plan(es.OP_SORT, es.INT32, n)
+    assert info["path_name"] == "radix"
+    _progress("1e9 int32: sorting")
+    out = to_np(es.sort(d_keys))
+    idx = to_np(es.argsort(d_keys, index_dtype=torch.int32)).astype(np.int64)
+    del d_keys
+    torch.cuda.empty_cache()
+    _progress("1e9 int32: oracle samples")
+    _check_ranks(keys, out, 6, 1)
+    _progress("1e9 int32: exact properties")
+    _check_argsort_exact(keys, out, idx)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dist", workloads.DISTRIBUTIONS)
+def test_distribution_sweep_1e8_int32(dist):
+    es = require_gpu()
+    n = 100_000_000
+    keys = workloads.make(dist, np.int32, n, 42 + workloads.DISTRIBUTIONS.index(dist))
+    d_keys = to_dev(keys)
+    out = to_np(es.sort(d_keys))
+    idx = to_np(es.argsort(d_keys))
+    _check_ranks(keys, out, 4, 2)
+    _check_argsort_exact(keys, out, idx)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dist", ["uniform", "distinct16"])
+def test_merge_routine_1e8_int32(dist):
+    es = require_gpu()
+    n = 100_000_000
+    keys = workloads.make(dist, np.int32, n, 7)
+    d_keys = to_dev(keys)
+    p = es.default_params(algo=es.ALGO_MERGE, fallback_threshold=0)
+    out = to_np(es.sort(d_keys, params=p))
+    idx = to_np(es.argsort(d_keys, params=p))
+    _check_ranks(keys, out, 3, 3)
+    _check_argsort_exact(keys, out, idx)
+
+
+def _gpu_sorted_int(t):
+    return bool((t[1:] >= t[:-1]).all().item())
+
+
+@pytest.mark.timeout(1200)
+def test_1e10_int32_keys():
+    es = require_gpu()
+    import torch
+
+    n = 10_000_000_000
+    free, _ = torch.cuda.mem_get_info()
+    if free < 140 * 2**30:
+        pytest.skip("needs about 140 GB of free HBM")
+    _progress("1e10 int32: generating")
+    keys = workloads.uniform(np.int32, n, workloads.DEFAULT_SEED)
+    d_keys = torch.empty(n, dtype=torch.int32, device="cuda")
+    step = 1 << 30
+    for s in range(0, n, step):
+        d_keys[s:s + step].copy_(torch.from_numpy(keys[s:s + step]))
+    info = es.plan(es.OP_SORT, es.INT32, n)
+    assert info["path_name"] == "radix" and info["status_bytes"] == 8
+    _progress("1e10 int32: sorting")
+    d_out = es.sort(d_keys)
+    torch.cuda.synchronize()
+    _progress("1e10 int32: properties on the GPU")
+    # ordered
+    for s in range(0, n - 1, step):
+        e = min(s + step + 1, n)
+        assert _gpu_sorted_int(d_out[s:e]), f"out of order in [{s}, {e})"
+    # same multiset: counts of every value of the top 16 bits, and of every
+    # value of the low 16 bits, agree (computed with torch.bincount)
+    for shift in (16, 0):
+        h_in = torch.zeros(65536, dtype=torch.int64, device="cuda")
+        h_out = torch.zeros_like(h_in)
+        for s in range(0, n, step):
+            for src, h in ((d_keys, h_in), (d_out, h_out)):
+                v = (src[s:s + step].to(torch.int64) + 2**31) >> shift & 0xFFFF
+                h += torch.bincount(v, minlength=65536)
+        assert torch.equal(h_in, h_out), f"multiset differs (bits {shift}..{shift + 15})"
+    _progress("1e10 int32: oracle samples")
+    out_host = np.empty(n, dtype=np.int32)
+    for s in range(0, n, step):
+        out_host[s:s + step] = d_out[s:s + step].cpu().numpy()
+    _check_ranks(keys, out_host, 2, 4)
+
+
+@pytest.mark.timeout(1200)
+def test_2e9_float64_pairs_with_index_payload():
+    es = require_gpu()
+    import torch
+
+    n = 2_000_000_000
+    free, _ = torch.cuda.mem_get_info()
+    if free < 90 * 2**30:
+        pytest.skip("needs about 90 GB of free HBM")
+    _progress("2e9 float64 pairs: generating")
+    keys = workloads.float_mix(np.float64, n, workloads.DEFAULT_SEED)
+    d_keys = torch.from_numpy(keys).cuda()
+    d_vals = torch.arange(n, dtype=torch.int32, device="cuda")
+    _progress("2e9 float64 pairs: sorting")
+    k_out, v_out = es.sort_pairs(d_keys, d_vals)
+    torch.cuda.synchronize()
+    del d_vals
+    _progress("2e9 float64 pairs: properties on the GPU")
+    step = 1 << 28
+    # values are a permutation of 0..n-1
+    seen = torch.zeros(n, dtype=torch.bool, device="cuda")
+    seen[v_out.to(torch.int64)] = True
+    assert bool(seen.all().item()), "payload is not a permutation"
+    del seen
+    # keys_out[j] has the bits of keys_in[v_out[j]]
+    kin_bits = d_keys.view(torch.int64)
+    kout_bits = k_out.view(torch.int64)
+    for s in range(0, n, step):
+        idx = v_out[s:s + step].to(torch.int64)
+        assert torch.equal(kin_bits[idx], kout_bits[s:s + step]), f"gathered keys differ in [{s}, {s + step})"
+    # (order key, index) strictly increasing: order key of a float64 bit
+    # pattern b is b with the sign bit flipped when b >= 0, else ~b; compare
+    # as signed after flipping the sign bit once more, i.e. b ^ (b>>63 & 0x7fff...) for b < 0
+    mag = torch.tensor(0x7FFFFFFFFFFFFFFF, dtype=torch.int64, device="cuda")
+    for s in range(0, n - 1, step):
+        e = min(s + step + 1, n)
+        b = kout_bits[s:e]
+        key = torch.where(b < 0, b ^ mag, b)  # signed total order of the float bit patterns
+        v = v_out[s:e]
+        ok = (key[1:] > key[:-1]) | ((key[1:] == key[:-1]) & (v[1:] > v[:-1]))
+        assert bool(ok.all().item()), f"not strictly increasing in [{s}, {e})"
+    _progress("2e9 float64 pairs: oracle samples")
+    out_host = k_out[: n].cpu().numpy()
+    _check_ranks(keys, out_host, 2, 5)
