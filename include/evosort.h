@@ -245,6 +245,71 @@ evosort_status evosort_merge_round(int dtype, const void *keys_in, void *keys_ou
                                    size_t temp_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Batches of arrays.                                                        */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Batched segmented sort.  Segment i is keys [offsets[i], offsets[i+1]) and is
+ * sorted on its own, ascending and stably: the result equals evosort_sort
+ * (evosort_sort_pairs) applied to each segment alone.
+ *
+ *   offsets    DEVICE array of nseg + 1 int64, non-decreasing, within [0, n],
+ *              every segment shorter than 2^30 keys.  Keys outside
+ *              [offsets[0], offsets[nseg]) are neither read nor written.
+ *              The offsets are checked on the device before anything else:
+ *              if any breaks these rules, no key or value is written and
+ *              evosort_check_device_error() returns EVOSORT_ERR_INVALID_ARG.
+ *   size classes  a segment shorter than fallback_threshold that fits one
+ *              workgroup (evosort_segmented_capacity) is sorted by one
+ *              workgroup in LDS (the small-array branch of Sec. 4.3,
+ *              Algorithm 6, per segment); longer segments take the
+ *              single-sweep LSD passes (Sec. 4, Algorithms 4 and 5), each
+ *              segment with its own digit histogram and chained scan.
+ *   params     digit_bits must be 8 and algo AUTO or RADIX
+ *              (EVOSORT_ERR_UNSUPPORTED_PARAM otherwise); block_threads and
+ *              items_per_thread pick the tile shape of the long segments.
+ *   graphs     the call is one fixed sequence of kernel launches: every
+ *              decision that depends on the segment sizes is taken on the
+ *              GPU, and nothing is allocated, synchronized or memset, so the
+ *              call can be captured in a HIP graph; a replay reads the
+ *              offsets, keys and values present at replay time.
+ *   temp       evosort_segmented_temp_bytes(dtype, n, nseg, value_bytes, p).
+ * In place is allowed for keys and for values.
+ */
+evosort_status evosort_segmented_temp_bytes(int dtype, int64_t n, int64_t nseg, uint32_t value_bytes,
+                                            const evosort_params *p, size_t *out_bytes);
+evosort_status evosort_segmented_sort(int dtype, const void *keys_in, void *keys_out, int64_t n,
+                                      const int64_t *offsets, int64_t nseg, void *temp, size_t temp_bytes,
+                                      const evosort_params *p, void *stream);
+evosort_status evosort_segmented_sort_pairs(int dtype, const void *keys_in, void *keys_out, const void *vals_in,
+                                            void *vals_out, uint32_t value_bytes, int64_t n,
+                                            const int64_t *offsets, int64_t nseg, void *temp, size_t temp_bytes,
+                                            const evosort_params *p, void *stream);
+
+/* Largest segment the one-workgroup classes take for (dtype, value_bytes). */
+evosort_status evosort_segmented_capacity(int dtype, uint32_t value_bytes, int64_t *out_keys);
+
+/*
+ * Synchronize `stream` and read what the last segmented call on `temp` did:
+ * class_counts[0..3] = segments per one-workgroup class (smallest first;
+ * unused classes 0), class_counts[4] = segments that took the radix passes;
+ * *tiles = radix tiles per pass.  Either output may be NULL.
+ */
+evosort_status evosort_segmented_stats(const void *temp, size_t temp_bytes, uint32_t *class_counts,
+                                       uint32_t *tiles, void *stream);
+
+/*
+ * The same batch sorted one segment at a time: one evosort_sort (values
+ * NULL, value_bytes 0) or evosort_sort_pairs per non-empty segment, in order,
+ * on `stream` -- the schedule the segmented sort replaces.  host_offsets is a
+ * HOST array of nseg + 1 int64 with the rules above.  temp as
+ * evosort_temp_bytes for the longest segment.
+ */
+evosort_status evosort_sort_each(int dtype, const void *keys_in, void *keys_out, const void *vals_in,
+                                 void *vals_out, uint32_t value_bytes, const int64_t *host_offsets, int64_t nseg,
+                                 void *temp, size_t temp_bytes, const evosort_params *p, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Errors and measurement.                                                   */
 /* ------------------------------------------------------------------------ */
 
@@ -255,9 +320,10 @@ const char *evosort_status_string(int status);
 int evosort_last_hip_error(void);
 
 /*
- * Synchronize `stream` and read the device error word a radix call left in
- * `temp`: EVOSORT_OK, or EVOSORT_ERR_DEVICE_TIMEOUT if a look-back wait ran
- * out of spin_limit.  temp/temp_bytes as passed to that call.
+ * Synchronize `stream` and read the device error word a radix or segmented
+ * call left in `temp`: EVOSORT_OK, EVOSORT_ERR_DEVICE_TIMEOUT if a look-back
+ * wait ran out of spin_limit, or EVOSORT_ERR_INVALID_ARG if segment offsets
+ * broke their rules.  temp/temp_bytes as passed to that call.
  */
 evosort_status evosort_check_device_error(const void *temp, size_t temp_bytes, void *stream);
 

@@ -16,6 +16,8 @@ stable sort (see the C file's header):
   steps of one LSD radix pass (Sec. 4, Algorithms 4 and 5, the block-based LSD radix sort);
 * :func:`insertion_chunks`, :func:`merge_round` -- the steps of the bottom-up
   mergesort (Sec. 4, Algorithm 3, the refined parallel mergesort);
+* :func:`segmented_sort`, :func:`segmented_sort_pairs` -- a batch of arrays
+  (segments of one buffer), each sorted on its own;
 * :func:`rank_of`, :func:`first_unsorted` -- sampled and property checks for
   sizes the full host sort is too slow for;
 * :func:`aps_path` -- which routine the adaptive partition sort picks
@@ -131,6 +133,41 @@ def sort_pairs(keys: np.ndarray, vals: np.ndarray):
 def argsort(keys: np.ndarray, index_dtype=np.int64) -> np.ndarray:
     """Result of an argsort: the stable permutation in the requested index type."""
     return stable_perm(keys).astype(index_dtype)
+
+
+def _segments(offsets, n: int):
+    offsets = np.asarray(offsets, dtype=np.int64)
+    if offsets.ndim != 1 or offsets.size < 1:
+        raise ValueError("offsets needs nseg + 1 entries")
+    if np.any(np.diff(offsets) < 0) or offsets[0] < 0 or offsets[-1] > n:
+        raise ValueError("offsets must be non-decreasing within [0, n]")
+    return zip(offsets[:-1].tolist(), offsets[1:].tolist())
+
+
+def segmented_sort(keys: np.ndarray, offsets) -> np.ndarray:
+    """Result of a batched segmented sort: every segment keys[offsets[i]:offsets[i+1]]
+    replaced by its own stable sort; keys outside the segments are unchanged."""
+    keys = _contig(keys)
+    out = keys.copy()
+    for b, e in _segments(offsets, keys.size):
+        if e - b > 1:
+            out[b:e] = sort(keys[b:e])
+    return out
+
+
+def segmented_sort_pairs(keys: np.ndarray, vals: np.ndarray, offsets):
+    """Key-value version of :func:`segmented_sort` (values travel with their keys)."""
+    keys = _contig(keys)
+    vals = _contig(vals)
+    if vals.shape[0] != keys.shape[0]:
+        raise ValueError("keys and values differ in length")
+    ko, vo = keys.copy(), vals.copy()
+    for b, e in _segments(offsets, keys.size):
+        if e - b > 1:
+            perm = stable_perm(keys[b:e])
+            ko[b:e] = keys[b:e][perm]
+            vo[b:e] = vals[b:e][perm]
+    return ko, vo
 
 
 def pass_count(dtype, digit_bits: int) -> int:

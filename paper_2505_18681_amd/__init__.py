@@ -12,6 +12,9 @@ Public calls (names follow the C ABI):
 * :func:`sort`, :func:`sort_pairs`, :func:`argsort` -- the three library sorts;
 * :func:`radix_histogram`, :func:`radix_pass`, :func:`merge_block_sort`,
   :func:`merge_round` -- single steps of the two routines;
+* :func:`segmented_sort`, :func:`segmented_sort_pairs` -- a batch of arrays
+  (segments of one buffer) in one fixed launch sequence; :func:`sort_each`
+  -- the same batch one plain sort per segment; :func:`segmented_stats`;
 * :func:`plan`, :func:`temp_bytes`, :func:`default_params` -- host-only queries;
 * :func:`profile_enable`, :func:`profile_reset`, :func:`profile_collect` --
   per-kernel HIP-event timing.
@@ -48,6 +51,8 @@ EXPORTED = (
     "evosort_argsort", "evosort_radix_histogram", "evosort_radix_pass", "evosort_merge_block_sort",
     "evosort_merge_round", "evosort_status_string", "evosort_last_hip_error", "evosort_check_device_error",
     "evosort_profile_enable", "evosort_profile_reset", "evosort_profile_collect", "evosort_profile_get",
+    "evosort_segmented_temp_bytes", "evosort_segmented_sort", "evosort_segmented_sort_pairs",
+    "evosort_segmented_capacity", "evosort_segmented_stats", "evosort_sort_each",
 )
 
 
@@ -115,6 +120,15 @@ _lib.evosort_profile_reset.restype = None
 _lib.evosort_profile_collect.argtypes = []
 _lib.evosort_profile_get.argtypes = [_i32, ctypes.c_char_p, _sz, ctypes.POINTER(ctypes.c_uint64),
                                      ctypes.POINTER(ctypes.c_double)]
+_lib.evosort_segmented_temp_bytes.argtypes = [_i32, _i64, _i64, _u32, _P, ctypes.POINTER(_sz)]
+_lib.evosort_segmented_sort.argtypes = [_i32, _vp, _vp, _i64, _vp, _i64, _vp, _sz, _P, _vp]
+_lib.evosort_segmented_sort_pairs.argtypes = [_i32, _vp, _vp, _vp, _vp, _u32, _i64, _vp, _i64, _vp, _sz, _P, _vp]
+_lib.evosort_segmented_capacity.argtypes = [_i32, _u32, ctypes.POINTER(_i64)]
+_lib.evosort_segmented_stats.argtypes = [_vp, _sz, ctypes.POINTER(_u32), ctypes.POINTER(_u32), _vp]
+_lib.evosort_sort_each.argtypes = [_i32, _vp, _vp, _vp, _vp, _u32, ctypes.POINTER(_i64), _i64, _vp, _sz, _P, _vp]
+for _f in ("evosort_segmented_temp_bytes", "evosort_segmented_sort", "evosort_segmented_sort_pairs",
+           "evosort_segmented_capacity", "evosort_segmented_stats", "evosort_sort_each"):
+    getattr(_lib, _f).restype = ctypes.c_int
 for _f in ("evosort_temp_bytes", "evosort_plan", "evosort_sort", "evosort_sort_pairs", "evosort_argsort",
            "evosort_radix_histogram", "evosort_radix_pass", "evosort_merge_block_sort", "evosort_merge_round",
            "evosort_last_hip_error", "evosort_check_device_error", "evosort_profile_collect", "evosort_profile_get"):
@@ -346,6 +360,124 @@ def merge_round(keys, values=None, *, run: int, stream=None):
                                         _ptr(vout) if vb else None, vb, n, run, _ptr(tmp), tmp.numel(),
                                         _stream(keys.device, stream)))
     return kout, vout
+
+
+# ---------------------------------------------------------- batches of arrays --
+def segmented_temp_bytes(dtype_code_: int, n: int, nseg: int, value_bytes: int = 0,
+                         params: Params | None = None) -> int:
+    out = _sz(0)
+    _check("evosort_segmented_temp_bytes",
+           _lib.evosort_segmented_temp_bytes(dtype_code_, n, nseg, value_bytes, _pp(params), ctypes.byref(out)))
+    return int(out.value)
+
+
+def segmented_capacity(dtype_code_: int, value_bytes: int = 0) -> int:
+    """Largest segment the one-workgroup classes sort."""
+    out = _i64(0)
+    _check("evosort_segmented_capacity", _lib.evosort_segmented_capacity(dtype_code_, value_bytes,
+                                                                         ctypes.byref(out)))
+    return int(out.value)
+
+
+def _offsets_tensor(offsets, device):
+    torch = _torch()
+    if not isinstance(offsets, torch.Tensor):
+        raise TypeError("offsets must be a torch.Tensor of int64 on the keys' device")
+    if offsets.dtype != torch.int64 or offsets.dim() != 1 or not offsets.is_contiguous():
+        raise ValueError("offsets must be a contiguous 1-D int64 tensor")
+    if offsets.device != device:
+        raise ValueError(f"offsets must be on {device} (got {offsets.device})")
+    if offsets.numel() < 1:
+        raise ValueError("offsets needs nseg + 1 >= 1 entries")
+    return offsets
+
+
+def segmented_sort(keys, offsets, *, params: Params | None = None, out=None, stream=None, temp=None):
+    """Each segment keys[offsets[i]:offsets[i+1]] sorted on its own (stable), in one launch sequence.
+
+    ``offsets`` is an int64 tensor on the keys' device.  Positions outside
+    [offsets[0], offsets[-1]) of ``out`` are left as they are.
+    """
+    torch = _torch()
+    keys = _key_tensor(keys)
+    offsets = _offsets_tensor(offsets, keys.device)
+    code = dtype_code(keys.dtype)
+    n, nseg = keys.numel(), offsets.numel() - 1
+    out = torch.empty_like(keys) if out is None else out
+    _key_tensor(out, "out")
+    if out.dtype != keys.dtype or out.numel() != n:
+        raise ValueError("out must match keys in dtype and length")
+    tmp = temp if temp is not None else _temp(segmented_temp_bytes(code, n, nseg, 0, params), keys.device)
+    with torch.cuda.device(keys.device):
+        _check("evosort_segmented_sort",
+               _lib.evosort_segmented_sort(code, _ptr(keys), _ptr(out), n, _ptr(offsets), nseg, _ptr(tmp),
+                                           tmp.numel(), _pp(params), _stream(keys.device, stream)))
+    return out
+
+
+def segmented_sort_pairs(keys, values, offsets, *, params: Params | None = None, keys_out=None, values_out=None,
+                         stream=None, temp=None):
+    """(keys, values) with each segment sorted stably by key, in one launch sequence."""
+    torch = _torch()
+    keys = _key_tensor(keys)
+    values = _key_tensor(values, "values")
+    offsets = _offsets_tensor(offsets, keys.device)
+    code = dtype_code(keys.dtype)
+    n, nseg = keys.numel(), offsets.numel() - 1
+    if values.numel() != n:
+        raise ValueError("keys and values differ in length")
+    vb = values.element_size()
+    if vb not in (4, 8):
+        raise TypeError("values must be 4- or 8-byte elements")
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    values_out = torch.empty_like(values) if values_out is None else values_out
+    tmp = temp if temp is not None else _temp(segmented_temp_bytes(code, n, nseg, vb, params), keys.device)
+    with torch.cuda.device(keys.device):
+        _check("evosort_segmented_sort_pairs",
+               _lib.evosort_segmented_sort_pairs(code, _ptr(keys), _ptr(keys_out), _ptr(values), _ptr(values_out),
+                                                 vb, n, _ptr(offsets), nseg, _ptr(tmp), tmp.numel(), _pp(params),
+                                                 _stream(keys.device, stream)))
+    return keys_out, values_out
+
+
+def segmented_stats(temp, *, stream=None) -> dict:
+    """What the last segmented call on ``temp`` did (synchronizes): class counts and radix tiles."""
+    torch = _torch()
+    counts = (_u32 * 5)()
+    tiles = _u32(0)
+    with torch.cuda.device(temp.device):
+        _check("evosort_segmented_stats", _lib.evosort_segmented_stats(_ptr(temp), temp.numel(), counts,
+                                                                       ctypes.byref(tiles),
+                                                                       _stream(temp.device, stream)))
+    return {"block_classes": [int(c) for c in counts[:4]], "large": int(counts[4]), "tiles": int(tiles.value)}
+
+
+def sort_each(keys, host_offsets, values=None, *, params: Params | None = None, out=None, values_out=None,
+              stream=None, temp=None):
+    """The batch sorted one plain sort per segment (``host_offsets``: a host sequence of nseg + 1 ints)."""
+    torch = _torch()
+    import numpy as np
+
+    keys = _key_tensor(keys)
+    code = dtype_code(keys.dtype)
+    offs = np.ascontiguousarray(np.asarray(host_offsets, dtype=np.int64))
+    nseg = offs.size - 1
+    out = torch.empty_like(keys) if out is None else out
+    vb = 0
+    if values is not None:
+        values = _key_tensor(values, "values")
+        vb = values.element_size()
+        values_out = torch.empty_like(values) if values_out is None else values_out
+    longest = int(np.max(np.diff(offs))) if nseg > 0 else 0
+    op = OP_SORT_PAIRS if vb else OP_SORT
+    tmp = temp if temp is not None else _temp(temp_bytes(op, code, longest, vb, params), keys.device)
+    with torch.cuda.device(keys.device):
+        _check("evosort_sort_each",
+               _lib.evosort_sort_each(code, _ptr(keys), _ptr(out), _ptr(values) if vb else None,
+                                      _ptr(values_out) if vb else None, vb,
+                                      offs.ctypes.data_as(ctypes.POINTER(_i64)), nseg, _ptr(tmp), tmp.numel(),
+                                      _pp(params), _stream(keys.device, stream)))
+    return (out, values_out) if vb else out
 
 
 def check_device_error(temp, *, stream=None) -> int:

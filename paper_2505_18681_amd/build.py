@@ -35,9 +35,13 @@ UNITS = [
     ("radix_host.hip", "radix_host.o", []),
     ("small_sort.hip", "small_sort.o", []),
     ("merge.hip", "merge.o", []),
+    ("segmented.hip", "segmented.o", []),
     ("capi.cpp", "capi.o", ["-x", "hip"]),
 ] + [
     ("radix_inst.hip", f"radix_k{kb}_v{vb}.o", [f"-DEVOSORT_KB={kb}", f"-DEVOSORT_VB={vb}"])
+    for kb in (4, 8) for vb in (0, 4, 8)
+] + [
+    ("seg_block.hip", f"seg_block_k{kb}_v{vb}.o", [f"-DEVOSORT_KB={kb}", f"-DEVOSORT_VB={vb}"])
     for kb in (4, 8) for vb in (0, 4, 8)
 ]
 

@@ -13,6 +13,7 @@
 #include "kernels.hpp"
 #include "merge.hpp"
 #include "radix_shapes.hpp"
+#include "segmented.hpp"
 #include "small_sort.hpp"
 
 using namespace evosort;
@@ -545,6 +546,245 @@ evosort_status sort_common(int op, int dtype, const void* keys_in, void* keys_ou
     }
 }
 
+
+// ------------------------------------------------------- segmented sort ----
+// Scratch of a batched call: the 256-byte header (error word, SegCounters),
+// the class lists, the large-segment table, the tile -> segment map, the
+// large segments' histograms and bases, the look-back words of every pass,
+// and one key (and value) buffer for the passes.  Only the header is zeroed
+// by the host sequence; histograms and look-back words are zeroed on the
+// device for the segments and tiles in use.
+struct SegPlan {
+    KeyDesc kd;
+    int vb;
+    int64_t n, nseg;
+    RadixShape shape;
+    uint32_t tile_keys;
+    int passes;
+    int classes;
+    int64_t caps[kSegMaxClasses];
+    int64_t block_limit;
+    uint64_t nlarge_max, tiles_max;
+    uint32_t spin_limit, debug_flags;
+    size_t off_ctr, off_lists, off_large, off_tile_slot, off_hist, off_bases, off_status, status_pass_bytes,
+        off_keys, off_vals, total;
+};
+
+constexpr uint32_t kSegHistGroup = 8;  // tiles per histogram workgroup
+
+evosort_status make_seg_plan(int dtype, int64_t n, int64_t nseg, uint32_t value_bytes, const evosort_params* pin,
+                             SegPlan* S)
+{
+    memset(S, 0, sizeof(*S));
+    evosort_params p;
+    if (pin) {
+        p = *pin;
+        evosort_status st = check_params(&p);
+        if (st != EVOSORT_OK)
+            return st;
+    } else {
+        default_params(&p);
+    }
+    bool is_int;
+    if (!key_desc(dtype, &S->kd, &is_int))
+        return EVOSORT_ERR_UNSUPPORTED_DTYPE;
+    if (value_bytes != 0 && value_bytes != 4 && value_bytes != 8)
+        return EVOSORT_ERR_UNSUPPORTED_DTYPE;
+    if (n < 0 || nseg < 0 || nseg >= ((int64_t)1 << 32) - 1)
+        return EVOSORT_ERR_INVALID_ARG;
+    if (p.digit_bits != (uint32_t)kSegBits || p.algo == EVOSORT_ALGO_MERGE)
+        return EVOSORT_ERR_UNSUPPORTED_PARAM;
+    const int kb = S->kd.bytes, vb = (int)value_bytes, rb = kb + vb;
+    S->vb = vb;
+    S->n = n;
+    S->nseg = nseg;
+    S->shape = p.block_threads ? RadixShape{(int)p.block_threads, (int)p.items_per_thread} : seg_default_shape(kb, vb);
+    if (!seg_pass_available(kb, vb, S->shape))
+        return EVOSORT_ERR_UNSUPPORTED_PARAM;
+    S->tile_keys = (uint32_t)(S->shape.threads * S->shape.items);
+    S->passes = (8 * kb) / kSegBits;
+    S->classes = seg_class_count(rb);
+    for (int c = 0; c < S->classes; ++c)
+        S->caps[c] = seg_class_capacity(rb, c);
+    const int64_t cap_max = seg_block_capacity(rb);
+    S->block_limit = p.fallback_threshold < (uint64_t)cap_max + 1 ? (int64_t)p.fallback_threshold : cap_max + 1;
+    S->spin_limit = p.spin_limit ? p.spin_limit : kDefaultSpinLimit;
+    S->debug_flags = p.debug_flags;
+    // Bounds from n and nseg alone: large segments hold >= max(block_limit, 1)
+    // keys; each adds at most one partial tile.
+    const int64_t least = S->block_limit > 1 ? S->block_limit : 1;
+    S->nlarge_max = (uint64_t)(n / least < nseg ? n / least : nseg);
+    S->tiles_max = (uint64_t)n / S->tile_keys + S->nlarge_max;
+    if (S->tiles_max > 0xffffffffull)
+        return EVOSORT_ERR_INVALID_ARG;
+
+    size_t off = kAlign;  // header: error word at 0, counters at 16
+    S->off_ctr = 16;
+    static_assert(16 + sizeof(SegCounters) <= kAlign, "counters fit in the header");
+    S->off_lists = off;
+    off = align_up(off + (size_t)(S->classes + 1) * (size_t)nseg * 4);
+    S->off_large = off;
+    off = align_up(off + (size_t)S->nlarge_max * sizeof(SegLarge));
+    S->off_tile_slot = off;
+    off = align_up(off + (size_t)S->tiles_max * 4);
+    const size_t slot_words = (size_t)S->passes * kSegBins;
+    S->off_hist = off;
+    off = align_up(off + (size_t)S->nlarge_max * slot_words * 4);
+    S->off_bases = off;
+    off = align_up(off + (size_t)S->nlarge_max * slot_words * 8);
+    S->status_pass_bytes = align_up((size_t)S->tiles_max * kSegBins * 4);
+    S->off_status = off;
+    off += (size_t)S->passes * S->status_pass_bytes;
+    S->off_keys = off;
+    off = align_up(off + (size_t)n * kb);
+    if (vb) {
+        S->off_vals = off;
+        off = align_up(off + (size_t)n * vb);
+    }
+    S->total = off;
+    return EVOSORT_OK;
+}
+
+evosort_status run_segmented(const SegPlan& S, const void* keys_in, void* keys_out, const void* vals_in,
+                             void* vals_out, const int64_t* offsets, void* temp, hipStream_t s)
+{
+    auto* ctr = reinterpret_cast<SegCounters*>(at(temp, S.off_ctr));
+    auto* err = reinterpret_cast<uint32_t*>(at(temp, 0));
+    auto* lists = reinterpret_cast<uint32_t*>(at(temp, S.off_lists));
+    auto* large = reinterpret_cast<SegLarge*>(at(temp, S.off_large));
+    auto* tile_slot = reinterpret_cast<uint32_t*>(at(temp, S.off_tile_slot));
+    auto* hist = reinterpret_cast<uint32_t*>(at(temp, S.off_hist));
+    auto* bases = reinterpret_cast<uint64_t*>(at(temp, S.off_bases));
+    const size_t slot_words = (size_t)S.passes * kSegBins;
+
+    EVOSORT_LAUNCH("fill_zero", s, launch_fill_zero(temp, kAlign, s));
+    if (S.nseg == 0)
+        return EVOSORT_OK;
+
+    SegClassifyArgs ca{};
+    ca.offsets = offsets;
+    ca.nseg = S.nseg;
+    ca.n = S.n;
+    ca.block_limit = S.block_limit;
+    ca.classes = S.classes;
+    for (int c = 0; c < S.classes; ++c)
+        ca.cap[c] = S.caps[c];
+    ca.tile_keys = S.tile_keys;
+    ca.ctr = ctr;
+    ca.lists = lists;
+    ca.large = large;
+    ca.error_word = err;
+    EVOSORT_LAUNCH("seg_classify", s, launch_seg_classify(ca, s));
+
+    // large segments: histograms and bases
+    const uint32_t slot_grid = (uint32_t)(S.nlarge_max < 2048 ? S.nlarge_max : 2048);
+    SegLargeArgs la{};
+    la.nlarge = &ctr->class_count[kSegMaxClasses];
+    la.large = large;
+    la.tile_slot = tile_slot;
+    la.hist = hist;
+    la.bases = bases;
+    la.passes = S.passes;
+    if (S.nlarge_max > 0) {
+        EVOSORT_LAUNCH("seg_setup", s, launch_seg_setup(la, S.tile_keys, slot_grid, s));
+        SegHistArgs ha{};
+        ha.keys = keys_in;
+        ha.tile_count = &ctr->tile_count;
+        ha.large = large;
+        ha.tile_slot = tile_slot;
+        ha.hist = hist;
+        ha.status = reinterpret_cast<uint32_t*>(at(temp, S.off_status));
+        ha.status_pass_words = S.status_pass_bytes / 4;
+        ha.tile_keys = S.tile_keys;
+        ha.group = kSegHistGroup;
+        ha.passes = S.passes;
+        const uint32_t hist_grid = (uint32_t)((S.tiles_max + kSegHistGroup - 1) / kSegHistGroup);
+        EVOSORT_LAUNCH("seg_histogram", s, launch_seg_histogram(S.kd, ha, hist_grid, s));
+        EVOSORT_LAUNCH("seg_scan", s, launch_seg_scan(la, slot_grid, s));
+    }
+
+    // small segments: one workgroup each, per class
+    for (int c = 0; c < S.classes; ++c) {
+        // class c holds segments longer than class c-1's capacity
+        const int64_t least = c == 0 ? 1 : S.caps[c - 1] + 1;
+        if (least >= S.block_limit)
+            break;
+        const int64_t bound = S.n / least < S.nseg ? S.n / least : S.nseg;
+        SegBlockArgs ba{};
+        ba.keys_in = keys_in;
+        ba.keys_out = keys_out;
+        ba.vals_in = vals_in;
+        ba.vals_out = vals_out;
+        ba.offsets = offsets;
+        ba.list = lists + (size_t)c * S.nseg;
+        ba.count = &ctr->class_count[c];
+        ba.ticket = &ctr->class_ticket[c];
+        EVOSORT_LAUNCH("seg_block_sort", s,
+                       launch_seg_block_sort(S.kd, S.vb, c, ba, (uint32_t)(bound < 0xffffffffLL ? bound : 0xffffffffLL),
+                                             s));
+    }
+
+    // large segments: the passes alternate between temp and the output so
+    // that the last (odd-numbered) pass writes the output
+    if (S.nlarge_max > 0) {
+        void* tk = at(temp, S.off_keys);
+        void* tv = S.vb ? at(temp, S.off_vals) : nullptr;
+        for (int p = 0; p < S.passes; ++p) {
+            SegPassArgs pa{};
+            RadixPassArgs& a = pa.base;
+            const bool to_temp = (p & 1) == 0;
+            a.keys_in = p == 0 ? keys_in : (to_temp ? keys_out : tk);
+            a.keys_out = to_temp ? tk : keys_out;
+            if (S.vb) {
+                a.vals_in = p == 0 ? vals_in : (to_temp ? vals_out : tv);
+                a.vals_out = to_temp ? tv : vals_out;
+            }
+            a.n = S.n;
+            a.shift = (uint32_t)(p * kSegBits);
+            a.bases = bases + (size_t)p * kSegBins;
+            a.status = at(temp, S.off_status + (size_t)p * S.status_pass_bytes);
+            a.tile_counter = &ctr->pass_ticket[p];
+            a.error_word = err;
+            a.flags = (S.debug_flags & EVOSORT_DEBUG_WITHHOLD_TILE0) ? RADIX_FLAG_WITHHOLD_T0 : 0u;
+            a.spin_limit = S.spin_limit;
+            a.tiles = 0;
+            pa.tile_slot = tile_slot;
+            pa.large = large;
+            pa.tile_count = &ctr->tile_count;
+            pa.slot_stride = (uint32_t)slot_words;
+            EVOSORT_LAUNCH("seg_radix_pass", s,
+                           launch_seg_radix_pass(S.kd, S.vb, S.shape, pa, (uint32_t)S.tiles_max, s));
+        }
+    }
+    return EVOSORT_OK;
+}
+
+evosort_status segmented_common(int dtype, const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
+                                uint32_t vb, int64_t n, const int64_t* offsets, int64_t nseg, void* temp,
+                                size_t temp_bytes, const evosort_params* p, void* stream)
+{
+    SegPlan S;
+    evosort_status st = make_seg_plan(dtype, n, nseg, vb, p, &S);
+    if (st != EVOSORT_OK)
+        return st;
+    if (nseg > 0 && !offsets)
+        return EVOSORT_ERR_INVALID_ARG;
+    if (n > 0 && (!keys_in || !keys_out || (vb && (!vals_in || !vals_out))))
+        return EVOSORT_ERR_INVALID_ARG;
+    if (temp_bytes < S.total)
+        return EVOSORT_ERR_TEMP_TOO_SMALL;
+    if (!temp || ((uintptr_t)temp & (kAlign - 1)))
+        return EVOSORT_ERR_INVALID_ARG;
+    const size_t kbytes = (size_t)n * S.kd.bytes, vbytes = (size_t)n * vb;
+    // buffers: 0 keys_in, 1 keys_out, 2 vals_in, 3 vals_out, 4 temp, 5 offsets
+    const void* bufs[6] = {keys_in, keys_out, vb ? vals_in : nullptr, vb ? vals_out : nullptr, temp, offsets};
+    const size_t sizes[6] = {kbytes, kbytes, vbytes, vbytes, S.total, (size_t)(nseg + 1) * 8};
+    st = check_buffers(bufs, sizes, 6, 0, 1, 2, 3);
+    if (st != EVOSORT_OK)
+        return st;
+    return run_segmented(S, keys_in, keys_out, vals_in, vals_out, offsets, temp,
+                         reinterpret_cast<hipStream_t>(stream));
+}
 }  // namespace
 
 // ===================================================================== ABI ===
@@ -775,6 +1015,107 @@ evosort_status evosort_merge_round(int dtype, const void* keys_in, void* keys_ou
     return EVOSORT_OK;
 }
 
+evosort_status evosort_segmented_temp_bytes(int dtype, int64_t n, int64_t nseg, uint32_t value_bytes,
+                                            const evosort_params* p, size_t* out_bytes)
+{
+    if (!out_bytes)
+        return EVOSORT_ERR_INVALID_ARG;
+    SegPlan S;
+    evosort_status st = make_seg_plan(dtype, n, nseg, value_bytes, p, &S);
+    if (st != EVOSORT_OK)
+        return st;
+    *out_bytes = S.total;
+    return EVOSORT_OK;
+}
+
+evosort_status evosort_segmented_sort(int dtype, const void* keys_in, void* keys_out, int64_t n,
+                                      const int64_t* offsets, int64_t nseg, void* temp, size_t temp_bytes,
+                                      const evosort_params* p, void* stream)
+{
+    return segmented_common(dtype, keys_in, keys_out, nullptr, nullptr, 0, n, offsets, nseg, temp, temp_bytes, p,
+                            stream);
+}
+
+evosort_status evosort_segmented_sort_pairs(int dtype, const void* keys_in, void* keys_out, const void* vals_in,
+                                            void* vals_out, uint32_t value_bytes, int64_t n,
+                                            const int64_t* offsets, int64_t nseg, void* temp, size_t temp_bytes,
+                                            const evosort_params* p, void* stream)
+{
+    if (value_bytes != 4 && value_bytes != 8)
+        return EVOSORT_ERR_UNSUPPORTED_DTYPE;
+    return segmented_common(dtype, keys_in, keys_out, vals_in, vals_out, value_bytes, n, offsets, nseg, temp,
+                            temp_bytes, p, stream);
+}
+
+evosort_status evosort_segmented_capacity(int dtype, uint32_t value_bytes, int64_t* out_keys)
+{
+    KeyDesc kd;
+    bool is_int;
+    if (!out_keys)
+        return EVOSORT_ERR_INVALID_ARG;
+    if (!key_desc(dtype, &kd, &is_int) || (value_bytes != 0 && value_bytes != 4 && value_bytes != 8))
+        return EVOSORT_ERR_UNSUPPORTED_DTYPE;
+    *out_keys = seg_block_capacity(kd.bytes + (int)value_bytes);
+    return EVOSORT_OK;
+}
+
+evosort_status evosort_segmented_stats(const void* temp, size_t temp_bytes, uint32_t* class_counts, uint32_t* tiles,
+                                       void* stream)
+{
+    if (!temp || temp_bytes < kAlign)
+        return EVOSORT_ERR_INVALID_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e);
+    SegCounters c;
+    e = hipMemcpy(&c, reinterpret_cast<const unsigned char*>(temp) + 16, sizeof(c), hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return hip_fail(e);
+    if (class_counts)
+        for (int i = 0; i <= kSegMaxClasses; ++i)
+            class_counts[i] = c.class_count[i];
+    if (tiles)
+        *tiles = c.tile_count;
+    return EVOSORT_OK;
+}
+
+evosort_status evosort_sort_each(int dtype, const void* keys_in, void* keys_out, const void* vals_in,
+                                 void* vals_out, uint32_t value_bytes, const int64_t* host_offsets, int64_t nseg,
+                                 void* temp, size_t temp_bytes, const evosort_params* p, void* stream)
+{
+    KeyDesc kd;
+    bool is_int;
+    if (!key_desc(dtype, &kd, &is_int))
+        return EVOSORT_ERR_UNSUPPORTED_DTYPE;
+    if (value_bytes != 0 && value_bytes != 4 && value_bytes != 8)
+        return EVOSORT_ERR_UNSUPPORTED_DTYPE;
+    if (nseg < 0 || (nseg > 0 && !host_offsets))
+        return EVOSORT_ERR_INVALID_ARG;
+    for (int64_t i = 0; i < nseg; ++i)
+        if (host_offsets[i] < 0 || host_offsets[i + 1] < host_offsets[i])
+            return EVOSORT_ERR_INVALID_ARG;
+    for (int64_t i = 0; i < nseg; ++i) {
+        const int64_t b = host_offsets[i], len = host_offsets[i + 1] - b;
+        if (len == 0)
+            continue;
+        const unsigned char* ki = reinterpret_cast<const unsigned char*>(keys_in) + (size_t)b * kd.bytes;
+        unsigned char* ko = reinterpret_cast<unsigned char*>(keys_out) + (size_t)b * kd.bytes;
+        evosort_status st;
+        if (value_bytes == 0) {
+            st = sort_common(EVOSORT_OP_SORT, dtype, ki, ko, nullptr, nullptr, 0, len, temp, temp_bytes, p, stream);
+        } else {
+            const unsigned char* vi = reinterpret_cast<const unsigned char*>(vals_in) + (size_t)b * value_bytes;
+            unsigned char* vo = reinterpret_cast<unsigned char*>(vals_out) + (size_t)b * value_bytes;
+            st = sort_common(EVOSORT_OP_SORT_PAIRS, dtype, ki, ko, vi, vo, value_bytes, len, temp, temp_bytes, p,
+                             stream);
+        }
+        if (st != EVOSORT_OK)
+            return st;
+    }
+    return EVOSORT_OK;
+}
+
 const char* evosort_status_string(int status)
 {
     switch (status) {
@@ -801,7 +1142,8 @@ int evosort_last_hip_error(void) { return t_last_hip; }
 
 evosort_status evosort_check_device_error(const void* temp, size_t temp_bytes, void* stream)
 {
-    // Every radix and mergesort scratch layout starts with the error word.
+    // Every radix, mergesort and segmented scratch layout starts with the
+    // error word.
     if (!temp || temp_bytes < 4)
         return EVOSORT_ERR_INVALID_ARG;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -812,6 +1154,8 @@ evosort_status evosort_check_device_error(const void* temp, size_t temp_bytes, v
     e = hipMemcpy(&word, temp, 4, hipMemcpyDeviceToHost);
     if (e != hipSuccess)
         return hip_fail(e);
+    if (word & kDeviceErrBadSegment)
+        return EVOSORT_ERR_INVALID_ARG;
     return word ? EVOSORT_ERR_DEVICE_TIMEOUT : EVOSORT_OK;
 }
 

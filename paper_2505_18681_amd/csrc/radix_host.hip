@@ -18,6 +18,13 @@ hipError_t radix_pass_dispatch_k8_v4(int, RadixShape, int, const KeyDesc&, const
 hipError_t radix_pass_dispatch_k8_v8(int, RadixShape, int, const KeyDesc&, const RadixPassArgs&, uint32_t,
                                      hipStream_t, bool*);
 
+hipError_t seg_pass_dispatch_k4_v0(RadixShape, const KeyDesc&, const SegPassArgs&, uint32_t, hipStream_t, bool*);
+hipError_t seg_pass_dispatch_k4_v4(RadixShape, const KeyDesc&, const SegPassArgs&, uint32_t, hipStream_t, bool*);
+hipError_t seg_pass_dispatch_k4_v8(RadixShape, const KeyDesc&, const SegPassArgs&, uint32_t, hipStream_t, bool*);
+hipError_t seg_pass_dispatch_k8_v0(RadixShape, const KeyDesc&, const SegPassArgs&, uint32_t, hipStream_t, bool*);
+hipError_t seg_pass_dispatch_k8_v4(RadixShape, const KeyDesc&, const SegPassArgs&, uint32_t, hipStream_t, bool*);
+hipError_t seg_pass_dispatch_k8_v8(RadixShape, const KeyDesc&, const SegPassArgs&, uint32_t, hipStream_t, bool*);
+
 namespace {
 constexpr int kHistThreads = 256;
 
@@ -126,6 +133,47 @@ hipError_t launch_radix_pass(const KeyDesc& kd, int val_bytes, int bits, RadixSh
             e = radix_pass_dispatch_k8_v4(bits, shape, status_bytes, kd, a, tiles, s, &found);
         else
             e = radix_pass_dispatch_k8_v8(bits, shape, status_bytes, kd, a, tiles, s, &found);
+    }
+    if (!found)
+        return hipErrorInvalidValue;
+    return e;
+}
+
+RadixShape seg_default_shape(int key_bytes, int val_bytes) { return radix_default_shape(key_bytes, val_bytes, kSegBits); }
+
+bool seg_pass_available(int key_bytes, int val_bytes, RadixShape sh)
+{
+    if ((key_bytes != 4 && key_bytes != 8) || (val_bytes != 0 && val_bytes != 4 && val_bytes != 8))
+        return false;
+    if (radix_lds_bytes(key_bytes, val_bytes, kSegBits, sh.threads, sh.items) > kLdsLimit)
+        return false;
+#define EVOSORT_MATCH_SEG_SHAPE(T, I)             \
+    if (sh.threads == (T) && sh.items == (I))     \
+        return true;
+    EVOSORT_SEG_SHAPES(EVOSORT_MATCH_SEG_SHAPE)
+#undef EVOSORT_MATCH_SEG_SHAPE
+    return false;
+}
+
+hipError_t launch_seg_radix_pass(const KeyDesc& kd, int val_bytes, RadixShape shape, const SegPassArgs& a,
+                                 uint32_t grid, hipStream_t s)
+{
+    bool found = false;
+    hipError_t e = hipErrorInvalidValue;
+    if (kd.bytes == 4) {
+        if (val_bytes == 0)
+            e = seg_pass_dispatch_k4_v0(shape, kd, a, grid, s, &found);
+        else if (val_bytes == 4)
+            e = seg_pass_dispatch_k4_v4(shape, kd, a, grid, s, &found);
+        else
+            e = seg_pass_dispatch_k4_v8(shape, kd, a, grid, s, &found);
+    } else {
+        if (val_bytes == 0)
+            e = seg_pass_dispatch_k8_v0(shape, kd, a, grid, s, &found);
+        else if (val_bytes == 4)
+            e = seg_pass_dispatch_k8_v4(shape, kd, a, grid, s, &found);
+        else
+            e = seg_pass_dispatch_k8_v8(shape, kd, a, grid, s, &found);
     }
     if (!found)
         return hipErrorInvalidValue;

@@ -17,6 +17,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "segmented.hpp"
 
 namespace evosort {
 
@@ -199,7 +200,7 @@ __device__ __forceinline__ uint64_t look_back(const ST* status, uint32_t tile, i
         ST x;
         while (((x = load_agent(&status[(size_t)(uint32_t)t * BINS + b])) >> Status<ST>::kShift) == 0) {
             if (++spins > spin_limit) {
-                atomicOr(error_word, 1u);
+                atomicOr(error_word, kDeviceErrTimeout);
                 return excl;
             }
             __builtin_amdgcn_s_sleep(1);
@@ -514,6 +515,51 @@ __global__ __launch_bounds__(THREADS) void radix_pass_kernel(RadixPassArgs a, Or
         pass_tile<false, KB, VB, BITS, THREADS, ITEMS, ST>(a, om, L, tile, tile_start, (uint32_t)left);
 }
 
+// One pass over the tiles of every large segment of a batched sort.  Tiles
+// are numbered globally, each segment's tiles consecutively, and handed out by
+// the ticket in that order.  A tile sees its segment as a whole array: its
+// keys, its digit bases and its look-back words start at the segment's first
+// key and first tile, so the chained scan of a segment starts at its own
+// first tile.  Exactly *tile_count workgroups take a ticket.
+template <int KB, int VB, int BITS, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void seg_radix_pass_kernel(SegPassArgs sa,
+                                                                 OrderMap<typename KeyWord<KB>::U> om)
+{
+    using ST = uint32_t;  // segments hold fewer than 2^30 keys
+    using U = typename KeyWord<KB>::U;
+    using V = typename ValWord<VB>::T;
+    using Lds = PassLds<KB, VB, BITS, THREADS, ITEMS>;
+    constexpr int TILE = THREADS * ITEMS;
+    constexpr int BINS = 1 << BITS;
+    __shared__ Lds L;
+
+    if (blockIdx.x >= *sa.tile_count)
+        return;  // uniform across the workgroup
+    if (threadIdx.x == 0)
+        L.next[0] = atomicAdd(sa.base.tile_counter, 1u);
+    __syncthreads();
+    const uint32_t t = L.next[0];
+    const uint32_t slot = sa.tile_slot[t];
+    const SegLarge g = sa.large[slot];
+    RadixPassArgs a = sa.base;
+    a.keys_in = reinterpret_cast<const U*>(sa.base.keys_in) + g.begin;
+    a.keys_out = reinterpret_cast<U*>(sa.base.keys_out) + g.begin;
+    if constexpr (VB != 0) {
+        a.vals_in = reinterpret_cast<const V*>(sa.base.vals_in) + g.begin;
+        a.vals_out = reinterpret_cast<V*>(sa.base.vals_out) + g.begin;
+    }
+    a.n = g.len;
+    a.bases = sa.base.bases + (size_t)slot * sa.slot_stride;
+    a.status = reinterpret_cast<ST*>(sa.base.status) + (size_t)g.first_tile * BINS;
+    const uint32_t lt = t - g.first_tile;
+    const int64_t tile_start = (int64_t)lt * TILE;
+    const int64_t left = (int64_t)g.len - tile_start;
+    if (left >= TILE)
+        pass_tile<true, KB, VB, BITS, THREADS, ITEMS, ST>(a, om, L, lt, tile_start, (uint32_t)TILE);
+    else
+        pass_tile<false, KB, VB, BITS, THREADS, ITEMS, ST>(a, om, L, lt, tile_start, (uint32_t)left);
+}
+
 // Workgroups resident at once on the current device for a kernel (cached per
 // kernel; the library serves one device at a time per process thread, and
 // all MI355X devices have the same count).
@@ -545,6 +591,17 @@ hipError_t launch_radix_pass_t(const KeyDesc& kd, const RadixPassArgs& a, uint32
     const uint32_t grid = tiles;
     (void)resident;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(THREADS), 0, s, a, om);
+    return hipGetLastError();
+}
+
+template <int KB, int VB, int BITS, int THREADS, int ITEMS>
+hipError_t launch_seg_radix_pass_t(const KeyDesc& kd, const SegPassArgs& a, uint32_t grid, hipStream_t s)
+{
+    using U = typename KeyWord<KB>::U;
+    OrderMap<U> om{(U)kd.flip, (U)kd.neg};
+    if (grid == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((seg_radix_pass_kernel<KB, VB, BITS, THREADS, ITEMS>), dim3(grid), dim3(THREADS), 0, s, a, om);
     return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@
 #define EVOSORT_CAT4(a, b, c, d) a##b##c##d
 #define EVOSORT_XCAT4(a, b, c, d) EVOSORT_CAT4(a, b, c, d)
 #define EVOSORT_NAME(kb, vb) EVOSORT_XCAT4(radix_pass_dispatch_k, kb, _v, vb)
+#define EVOSORT_SEG_NAME(kb, vb) EVOSORT_XCAT4(seg_pass_dispatch_k, kb, _v, vb)
 
 namespace evosort {
 
@@ -97,6 +98,24 @@ hipError_t EVOSORT_NAME(EVOSORT_KB, EVOSORT_VB)(int bits, RadixShape sh, int sta
         return by_shape<uint32_t>(bits, sh, kd, a, tiles, s, found);
     if (status_bytes == 8)
         return by_shape<uint64_t>(bits, sh, kd, a, tiles, s, found);
+    return hipSuccess;
+}
+
+// Segmented pass for (EVOSORT_KB, EVOSORT_VB) at 8-bit digits; *found tells
+// whether the shape is compiled in.
+hipError_t EVOSORT_SEG_NAME(EVOSORT_KB, EVOSORT_VB)(RadixShape sh, const KeyDesc& kd, const SegPassArgs& a,
+                                                     uint32_t grid, hipStream_t s, bool* found)
+{
+    *found = false;
+#define EVOSORT_TRY_SEG_SHAPE(T, I)                                                                     \
+    if constexpr (radix_lds_bytes(EVOSORT_KB, EVOSORT_VB, kSegBits, (T), (I)) <= kLdsLimit) {           \
+        if (sh.threads == (T) && sh.items == (I)) {                                                     \
+            *found = true;                                                                              \
+            return launch_seg_radix_pass_t<EVOSORT_KB, EVOSORT_VB, kSegBits, (T), (I)>(kd, a, grid, s); \
+        }                                                                                               \
+    }
+    EVOSORT_SEG_SHAPES(EVOSORT_TRY_SEG_SHAPE)
+#undef EVOSORT_TRY_SEG_SHAPE
     return hipSuccess;
 }
 

@@ -41,4 +41,8 @@ constexpr RadixShape kRadixFallbackShape{256, 8};
 #define EVOSORT_RADIX_ALT_SHAPES(X) \
     X(256, 8) X(256, 12) X(256, 16) X(256, 24) X(256, 32) X(256, 48) X(512, 8) X(512, 16) X(512, 24) X(512, 32) X(1024, 16)
 
+// Tile shapes of the segmented pass (8-bit digits, 32-bit look-back words),
+// compiled where they fit in LDS.
+#define EVOSORT_SEG_SHAPES(X) X(512, 24) X(512, 16) X(256, 16) X(256, 8)
+
 }  // namespace evosort

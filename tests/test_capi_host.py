@@ -199,3 +199,42 @@ def test_pairs_and_argsort_argument_errors():
                                    None) == es.ERR_INVALID_ARG  # run < 1
     assert lib.evosort_radix_histogram(es.INT32, FAKE, 1000, 3, FAKE + big, None, None, 0,
                                        None) == es.ERR_INVALID_ARG
+
+
+def test_segmented_plan_and_argument_errors():
+    big = 1 << 40
+    lib = es._lib
+    assert es.segmented_capacity(es.UINT32, 0) == 16384
+    assert es.segmented_capacity(es.INT64, 0) == es.segmented_capacity(es.INT32, 4) == 8192
+    assert es.segmented_capacity(es.FLOAT64, 8) == es.segmented_capacity(es.FLOAT32, 8) == 4096
+    # scratch grows with n and with the number of segments
+    t1 = es.segmented_temp_bytes(es.UINT32, 10**6, 100)
+    assert es.segmented_temp_bytes(es.UINT32, 2 * 10**6, 100) > t1
+    assert es.segmented_temp_bytes(es.UINT32, 10**6, 1000) > t1
+    assert es.segmented_temp_bytes(es.UINT32, 10**6, 100, 4) > t1
+    # the segmented routine is radix-only with 8-bit digits
+    for kw in ({"digit_bits": 11}, {"algo": es.ALGO_MERGE}, {"block_threads": 128, "items_per_thread": 7}):
+        with pytest.raises(es.EvosortError) as e:
+            es.segmented_temp_bytes(es.UINT32, 10**6, 100, 0, es.default_params(**kw))
+        assert e.value.status == es.ERR_UNSUPPORTED_PARAM, kw
+    need = es.segmented_temp_bytes(es.UINT32, 10**6, 100)
+    seg = lib.evosort_segmented_sort
+    assert seg(es.UINT32, FAKE, FAKE + big, 10**6, FAKE + 3 * big, -1, FAKE + 2 * big, need, None,
+               None) == es.ERR_INVALID_ARG
+    assert seg(es.UINT32, FAKE, FAKE + big, 10**6, None, 100, FAKE + 2 * big, need, None, None) == es.ERR_INVALID_ARG
+    assert seg(es.UINT32, FAKE, FAKE + big, 10**6, FAKE + 3 * big, 100, FAKE + 2 * big, need - 1, None,
+               None) == es.ERR_TEMP_TOO_SMALL
+    assert seg(99, FAKE, FAKE + big, 10**6, FAKE + 3 * big, 100, FAKE + 2 * big, need, None,
+               None) == es.ERR_UNSUPPORTED_DTYPE
+    # offsets inside the keys, temp overlapping the output
+    assert seg(es.UINT32, FAKE, FAKE + big, 10**6, FAKE + 64, 100, FAKE + 2 * big, need, None,
+               None) == es.ERR_INVALID_ARG
+    assert seg(es.UINT32, FAKE, FAKE + big, 10**6, FAKE + 3 * big, 100, FAKE + big + 256, need, None,
+               None) == es.ERR_INVALID_ARG
+    assert lib.evosort_segmented_sort_pairs(es.UINT32, FAKE, FAKE + big, FAKE + 4 * big, FAKE + 5 * big, 2, 10**6,
+                                            FAKE + 3 * big, 100, FAKE + 2 * big, big, None,
+                                            None) == es.ERR_UNSUPPORTED_DTYPE
+    # one-by-one schedule: host offsets are checked before anything is enqueued
+    offs = (ctypes.c_int64 * 3)(0, 10, 5)
+    assert lib.evosort_sort_each(es.UINT32, FAKE, FAKE + big, None, None, 0, offs, 2, FAKE + 2 * big, big, None,
+                                 None) == es.ERR_INVALID_ARG

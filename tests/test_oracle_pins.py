@@ -310,3 +310,53 @@ def test_struct_roundtrip_sanity():
     # the float golden file's hex patterns are the standard encodings
     assert struct.unpack("<f", struct.pack("<I", 0x3FC00000))[0] == 1.5
     assert struct.unpack("<d", struct.pack("<Q", 0x3FF8000000000000))[0] == 1.5
+
+
+# --------------------------------------------------------------------------
+# Batches of arrays (segmented sort)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dt", INT_DTYPES)
+def test_segmented_sort_equals_numpy_per_segment(dt):
+    """Each segment equals numpy's stable sort of that segment; keys outside the segments are untouched."""
+    sizes = workloads.segment_sizes(300, seed=3, median=40, sigma=1.5, lo=0, hi=3000)
+    offs = workloads.segment_offsets(sizes) + 5  # a gap before the first segment
+    n = int(offs[-1]) + 7                        # and one after the last
+    keys = workloads.uniform(dt, n, 11) % 97     # many equal keys
+    got = oracle.segmented_sort(keys, offs)
+    assert np.array_equal(got[:5], keys[:5]) and np.array_equal(got[offs[-1]:], keys[offs[-1]:])
+    for b, e in zip(offs[:-1], offs[1:]):
+        assert np.array_equal(got[b:e], np.sort(keys[b:e], kind="stable"))
+
+
+def test_segmented_pairs_follow_numpy_stable_argsort():
+    sizes = np.array([0, 1, 2, 17, 0, 300, 5, 1000, 3], dtype=np.int64)
+    offs = workloads.segment_offsets(sizes)
+    keys = workloads.distinct16(np.int64, int(offs[-1]), 4)
+    vals = np.arange(keys.size, dtype=np.uint32) * 3 + 1
+    ko, vo = oracle.segmented_sort_pairs(keys, vals, offs)
+    for b, e in zip(offs[:-1], offs[1:]):
+        p = np.argsort(keys[b:e], kind="stable")
+        assert np.array_equal(ko[b:e], keys[b:e][p]) and np.array_equal(vo[b:e], vals[b:e][p])
+
+
+def test_segmented_degenerate_cases():
+    keys = workloads.uniform(np.float32, 500, 9)
+    # one segment over everything: the plain sort
+    assert np.array_equal(oracle.segmented_sort(keys, [0, 500]).view(np.uint32), oracle.sort(keys).view(np.uint32))
+    # segments of one key, or none: unchanged
+    assert np.array_equal(oracle.segmented_sort(keys, np.arange(501)).view(np.uint32), keys.view(np.uint32))
+    assert np.array_equal(oracle.segmented_sort(keys, [250]).view(np.uint32), keys.view(np.uint32))
+    with pytest.raises(ValueError):
+        oracle.segmented_sort(keys, [0, 300, 200])
+    with pytest.raises(ValueError):
+        oracle.segmented_sort(keys, [0, 501])
+
+
+def test_segment_sizes_recipe():
+    """Log-normal sizes: the median and the spread of log sizes follow the parameters; clipping holds."""
+    s = workloads.segment_sizes(100_000, seed=42)
+    assert s.min() >= 16 and s.max() <= 4_000_000
+    assert abs(np.median(s) / 2048 - 1) < 0.05
+    inner = s[(s > 16) & (s < 4_000_000)]
+    assert abs(np.std(np.log(inner)) - 2.0) < 0.1  # clipping trims the tails a little
+    assert np.array_equal(workloads.segment_offsets([3, 0, 2]), [0, 3, 3, 5])

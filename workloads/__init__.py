@@ -19,6 +19,10 @@ fixed seed, 42 by default, Sec. 7.5 and the data availability statement):
 * ``all_equal``      -- every key 42;
 * ``float_mix``      -- N(0, 1) with a fraction replaced by values drawn from
                         {-inf, +inf, -0.0, +0.0} (no NaN).
+
+Batches of arrays: :func:`segment_sizes` draws log-normal array sizes
+(round(exp(N(ln median, sigma))), clipped), :func:`segment_offsets` turns sizes
+into the nseg + 1 offsets of one buffer.
 """
 from __future__ import annotations
 
@@ -187,3 +191,22 @@ def make(dist: str, dtype, n: int, seed: int = DEFAULT_SEED) -> np.ndarray:
     if dist == "float_mix":
         return float_mix(dtype, n, seed)
     raise ValueError(f"unknown distribution {dist!r}")
+
+
+def segment_sizes(nseg: int, seed: int = DEFAULT_SEED, median: float = 2048.0, sigma: float = 2.0,
+                  lo: int = 16, hi: int = 4_000_000) -> np.ndarray:
+    """``nseg`` array sizes: round(exp(N(ln median, sigma))) clipped to [lo, hi] (int64).
+
+    ``sigma`` is in natural-log units.
+    """
+    g = rng(seed)
+    sizes = np.rint(np.exp(g.normal(np.log(median), sigma, size=nseg)))
+    return np.clip(sizes, lo, hi).astype(np.int64)
+
+
+def segment_offsets(sizes) -> np.ndarray:
+    """Offsets (int64, len(sizes) + 1) of segments of the given sizes laid end to end from 0."""
+    sizes = np.asarray(sizes, dtype=np.int64)
+    out = np.zeros(sizes.size + 1, dtype=np.int64)
+    np.cumsum(sizes, out=out[1:])
+    return out
