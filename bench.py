@@ -17,7 +17,10 @@ Prints one JSON line with the contract fields plus:
   cpu_baseline  the CPU oracle (single-threaded stable mergesort) timed on a
                 bounded sample of the same workload on the host;
   kernels       mean milliseconds per launch of every library kernel;
-  secondary     the same measurement for 1e9 int64 keys (unless --no-secondary).
+  secondary     the same measurement for 1e9 int64 keys (unless --no-secondary);
+  batched       100k uint32 arrays of log-normal sizes sorted by one segmented
+                call, by its HIP-graph replay and by one plain sort per array
+                (unless --no-batched).
 """
 from __future__ import annotations
 
@@ -147,6 +150,102 @@ def run_sort_bench(es, torch, dtype_name: str, n: int, steps: int, warmup: int, 
     }
 
 
+def run_batched_bench(es, torch, nseg: int, steps: int, warmup: int, seed: int, each_steps: int = 1):
+    """Batched segmented sort of `nseg` uint32 arrays with log-normal sizes, against one plain sort per array.
+
+    Three schedules of the same batch, from the same resident input buffer:
+      segmented  one evosort_segmented_sort call (fixed launch sequence);
+      graph      that call captured once in a HIP graph and replayed;
+      per_array  evosort_sort_each: one evosort_sort per array, in order.
+    All three must produce identical bytes (checked on the device).
+    """
+    import numpy as np
+
+    import workloads
+
+    sizes = workloads.segment_sizes(nseg, seed)
+    offs = workloads.segment_offsets(sizes)
+    total = int(offs[-1])
+    host = workloads.uniform(np.uint32, total, seed)
+    keys = torch.from_numpy(host.view(np.int32)).cuda().view(torch.uint32)
+    del host
+    offsets = torch.from_numpy(offs).cuda()
+    out = torch.empty_like(keys)
+    ref = torch.empty_like(keys)
+    params = es.default_params()
+    temp = torch.empty(es.segmented_temp_bytes(es.UINT32, total, nseg, 0, params), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, k):
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(k):
+            fn()
+        stop.record(stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) / k
+
+    seg = lambda: es.segmented_sort(keys, offsets, params=params, out=out, temp=temp)  # noqa: E731
+    for _ in range(warmup):
+        seg()
+    torch.cuda.synchronize()
+    stats = es.segmented_stats(temp)
+    es.profile_reset()
+    es.profile_enable(True)
+    seg_ms = timed(seg, steps)
+    es.profile_enable(False)
+    kernels = es.profile_collect()
+    es.profile_reset()
+
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        seg()  # warm the allocator-free path on the capture stream
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        seg()
+    graph.replay()
+    torch.cuda.synchronize()
+    graph_ms = timed(graph.replay, steps)
+    graph_equal = True  # compared below against the eager output
+
+    seg_out = out.clone()
+    each_temp = torch.empty(max(es.temp_bytes(es.OP_SORT, es.UINT32, int(sizes.max()), 0, params), 256),
+                            dtype=torch.uint8, device="cuda")
+    each = lambda: es.sort_each(keys, offs, params=params, out=ref, temp=each_temp)  # noqa: E731
+    each()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    each_ms = timed(each, each_steps)
+    each_wall_ms = (time.perf_counter() - t0) * 1e3 / each_steps
+    same = bool(torch.equal(seg_out.view(torch.int32), ref.view(torch.int32)))
+    graph.replay()
+    torch.cuda.synchronize()
+    graph_equal = bool(torch.equal(out.view(torch.int32), ref.view(torch.int32)))
+    if not (same and graph_equal):
+        raise RuntimeError("segmented, graph and per-array outputs differ")
+    del keys, out, ref, temp, each_temp, offsets, graph
+    torch.cuda.empty_cache()
+    per_kernel = {k: round(v[1] / v[0], 4) for k, v in kernels.items() if v[0]}
+    per_kernel_calls = {k: v[0] // max(steps, 1) for k, v in kernels.items() if v[0]}
+    return {
+        "workload": f"{nseg} uint32 arrays, log-normal sizes (median 2048, sigma 2, clipped to [16, 4e6]), "
+                    f"{total} keys in all, uniform keys, keys-only, one buffer",
+        "nseg": nseg, "keys": total,
+        "value": round(nseg / (graph_ms * 1e-3), 1), "unit": "segs/s",
+        "gkeys_per_s": round(total / (graph_ms * 1e-3) / 1e9, 3),
+        "ms": {"segmented": round(seg_ms, 3), "graph": round(graph_ms, 3), "per_array": round(each_ms, 3),
+               "per_array_host_wall": round(each_wall_ms, 3)},
+        "speedup_vs_per_array": round(each_ms / graph_ms, 2),
+        "size_classes": stats,
+        "kernels_ms": per_kernel, "launches_per_call": per_kernel_calls,
+        "identical_bytes": True,
+    }
+
+
 def cpu_baseline(dtype_name: str, n_sample: int, seed: int):
     """The oracle, untuned, on a bounded sample of the same workload (one host thread)."""
     import numpy as np
@@ -179,6 +278,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=100_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-nseg", type=int, default=100_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (for counter calibration runs)")
     args = ap.parse_args()
@@ -218,6 +319,11 @@ def main():
         }
         print(f"# int64: {sec['ms_per_step']:.3f} ms/step, {sec['gkeys_per_s']:.2f} Gkeys/s", file=sys.stderr,
               flush=True)
+
+    batched = None
+    if not args.no_batched:
+        batched = run_batched_bench(es, torch, args.batched_nseg, max(2, args.steps // 2), 1, args.seed)
+        print(f"# batched: {batched['ms']}", file=sys.stderr, flush=True)
 
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -269,6 +375,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels_ms": main_res["kernels_ms"],
         "secondary": secondary,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
 

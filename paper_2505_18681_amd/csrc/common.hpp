@@ -79,6 +79,15 @@ __device__ __forceinline__ uint32_t after(uint32_t x, uint32_t y)
     return x;
 }
 
+// Returns x unchanged, computed at this point: the compiler may not defer the
+// arithmetic that produces x to its first use.  Used where deferring would keep
+// the operands of x (several registers) alive instead of x itself.
+__device__ __forceinline__ uint32_t materialize(uint32_t x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // All ones if bit b of x is set, else zero (a sign-extended 1-bit field).
 // Written as one instruction so that the compiler tests this value for the
 // ballot instead of re-deriving the bit with a shift and a compare.

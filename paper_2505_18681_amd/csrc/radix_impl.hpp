@@ -335,7 +335,9 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
                 bkt[d] = 0;
                 wh[d] = old + (uint32_t)__popcll(peers);
             }
-            rk[i] = (d << 16) | (old + below);
+            // packed now: a deferred pack would keep d, old and below
+            // alive per item (three registers instead of one)
+            rk[i] = materialize((d << 16) | (old + below));
         }
     } else {
         // Wide digits (the buckets would not fit in LDS): the same peer mask
@@ -362,7 +364,9 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
             const uint32_t old = wh[d];
             if ((FULL || valid) && below == 0)
                 wh[d] = old + (uint32_t)(__builtin_popcount(plo) + __builtin_popcount(phi));
-            rk[i] = (d << 16) | (old + below);
+            // packed now: a deferred pack would keep d, old and below
+            // alive per item (three registers instead of one)
+            rk[i] = materialize((d << 16) | (old + below));
         }
     }
     __syncthreads();
