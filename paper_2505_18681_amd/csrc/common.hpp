@@ -88,6 +88,15 @@ __device__ __forceinline__ uint32_t materialize(uint32_t x)
     return x;
 }
 
+// base[idx] for a 32-bit index: the byte offset is formed in 32 bits, so the
+// load takes one offset register and a base held in scalar registers instead
+// of a 64-bit address per element.  Requires idx * sizeof(T) < 2^32.
+template <typename T>
+__device__ __forceinline__ T load_off32(const T* base, uint32_t idx)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T)));
+}
+
 // All ones if bit b of x is set, else zero (a sign-extended 1-bit field).
 // Written as one instruction so that the compiler tests this value for the
 // ballot instead of re-deriving the bit with a shift and a compare.

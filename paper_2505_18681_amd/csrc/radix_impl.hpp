@@ -280,7 +280,7 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t off = off0 + (uint32_t)(i * kWave);
-        k[i] = tile_keys[FULL ? off : (off < nvalid ? off : nvalid - 1)];
+        k[i] = load_off32(tile_keys, FULL ? off : min(off, nvalid - 1));
     }
     if constexpr (VB != 0) {
         const V* __restrict__ tile_vals = reinterpret_cast<const V*>(a.vals_in) + tile_start;
@@ -291,7 +291,7 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
             if (iota)
                 v[i] = (V)(tile_start + off);
             else
-                v[i] = tile_vals[FULL ? off : (off < nvalid ? off : nvalid - 1)];
+                v[i] = load_off32(tile_vals, FULL ? off : min(off, nvalid - 1));
         }
     }
 
@@ -320,13 +320,13 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
     uint32_t rk[ITEMS];
     if constexpr (Lds::kBuckets) {
         uint64_t* bkt = reinterpret_cast<uint64_t*>(L.uni + Lds::BUCKET_OFFSET) + w * BINS;
-        const uint64_t my_bit = 1ull << lane;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t d = (uint32_t)((om.to_order(k[i]) >> a.shift) & (U)(BINS - 1));
             const bool valid = item_valid(i);
+            // each lane sets its bit in the 32-bit half of the bucket that holds it
             if (FULL || valid)
-                atomicOr(reinterpret_cast<unsigned long long*>(&bkt[d]), (unsigned long long)my_bit);
+                atomicOr(reinterpret_cast<uint32_t*>(&bkt[d]) + (lane >> 5), 1u << (lane & 31));
             const uint64_t peers = bkt[d];
             const uint32_t old = wh[d];
             const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
@@ -542,9 +542,16 @@ __global__ __launch_bounds__(THREADS) void seg_radix_pass_kernel(SegPassArgs sa,
     if (threadIdx.x == 0)
         L.next[0] = atomicAdd(sa.base.tile_counter, 1u);
     __syncthreads();
-    const uint32_t t = L.next[0];
-    const uint32_t slot = sa.tile_slot[t];
-    const SegLarge g = sa.large[slot];
+    // The ticket is the same in every lane; saying so (and the same for the
+    // segment's fields) keeps the segment's description and pointers in
+    // scalar registers.
+    const uint32_t t = __builtin_amdgcn_readfirstlane(L.next[0]);
+    const uint32_t slot = __builtin_amdgcn_readfirstlane(sa.tile_slot[t]);
+    SegLarge g = sa.large[slot];
+    g.begin = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)g.begin >> 32)) << 32) |
+                        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)g.begin));
+    g.len = __builtin_amdgcn_readfirstlane(g.len);
+    g.first_tile = __builtin_amdgcn_readfirstlane(g.first_tile);
     RadixPassArgs a = sa.base;
     a.keys_in = reinterpret_cast<const U*>(sa.base.keys_in) + g.begin;
     a.keys_out = reinterpret_cast<U*>(sa.base.keys_out) + g.begin;
@@ -592,7 +599,7 @@ hipError_t launch_radix_pass_t(const KeyDesc& kd, const RadixPassArgs& a, uint32
     auto kernel = radix_pass_kernel<KB, VB, BITS, THREADS, ITEMS, ST>;
     static int cached = 0;  // one per instantiation
     const uint32_t resident = (uint32_t)resident_groups(kernel, THREADS, cached);
-    const uint32_t grid = tiles;
+    const uint32_t grid = tiles;  // one workgroup per tile
     (void)resident;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(THREADS), 0, s, a, om);
     return hipGetLastError();
