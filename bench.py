@@ -20,7 +20,9 @@ Prints one JSON line with the contract fields plus:
   secondary     the same measurement for 1e9 int64 keys (unless --no-secondary);
   batched       100k uint32 arrays of log-normal sizes sorted by one segmented
                 call, by its HIP-graph replay and by one plain sort per array
-                (unless --no-batched).
+                (unless --no-batched);
+  tuned         GA-tuned parameters per distribution of the 1e8 int32 sweep
+                against the defaults (unless --no-tuned).
 """
 from __future__ import annotations
 
@@ -246,6 +248,35 @@ def run_batched_bench(es, torch, nseg: int, steps: int, warmup: int, seed: int, 
     }
 
 
+def run_tuned_bench(es, torch, n: int, seed: int, pop: int, generations: int, reps: int):
+    """GA-tuned parameters per distribution (the distribution sweep), against the library defaults.
+
+    For each distribution a reduced GA (Algorithm 2's operators, `pop` x
+    `generations`) times sorts of n int32 keys; the entry reports the tuned
+    parameters, the tuned time and the default time, both re-timed after the
+    search.  Every candidate's output is checked bit for bit against the first.
+    """
+    import numpy as np
+
+    import workloads
+    from paper_2505_18681_amd import tuner
+
+    out = []
+    t0 = time.perf_counter()
+    for dist in workloads.DISTRIBUTIONS:
+        keys = torch.from_numpy(workloads.make(dist, np.int32, n, seed)).cuda()
+        e = tuner.tune_sort(es, keys, seed=seed, pop_size=pop, generations=generations, reps=reps)
+        out.append({"dist": dist, "params": e["params"], "ms": e["ms"], "default_ms": e["default_ms"],
+                    "speedup": round(e["default_ms"] / e["ms"], 3) if e["ms"] else None,
+                    "gkeys_per_s": round(n / (e["ms"] * 1e-3) / 1e9, 2) if e["ms"] else None,
+                    "evaluations": e["evaluations"]})
+        del keys
+        torch.cuda.empty_cache()
+    return {"workload": f"int32 distribution sweep at {n:.0e} keys each, GA with population {pop} over "
+                        f"{generations} generations, median of {reps} timed sorts per candidate",
+            "entries": out, "search_s": round(time.perf_counter() - t0, 1)}
+
+
 def cpu_baseline(dtype_name: str, n_sample: int, seed: int):
     """The oracle, untuned, on a bounded sample of the same workload (one host thread)."""
     import numpy as np
@@ -280,6 +311,10 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-nseg", type=int, default=100_000)
+    ap.add_argument("--no-tuned", action="store_true")
+    ap.add_argument("--tuned-n", type=int, default=100_000_000)
+    ap.add_argument("--tuned-pop", type=int, default=10)
+    ap.add_argument("--tuned-generations", type=int, default=4)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (for counter calibration runs)")
     args = ap.parse_args()
@@ -324,6 +359,12 @@ def main():
     if not args.no_batched:
         batched = run_batched_bench(es, torch, args.batched_nseg, max(2, args.steps // 2), 1, args.seed)
         print(f"# batched: {batched['ms']}", file=sys.stderr, flush=True)
+
+    tuned = None
+    if not args.no_tuned:
+        tuned = run_tuned_bench(es, torch, args.tuned_n, args.seed, args.tuned_pop, args.tuned_generations, 2)
+        print(f"# tuned: {[(e['dist'], e['ms'], e['default_ms']) for e in tuned['entries']]}", file=sys.stderr,
+              flush=True)
 
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -376,6 +417,7 @@ def main():
         "kernels_ms": main_res["kernels_ms"],
         "secondary": secondary,
         "batched": batched,
+        "tuned": tuned,
     }
     print(json.dumps(line), flush=True)
 

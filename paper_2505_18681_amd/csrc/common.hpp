@@ -71,6 +71,21 @@ __device__ __forceinline__ uint32_t keep_equal_bits(uint32_t acc, uint32_t m, ui
     return __builtin_amdgcn_bitop3_b32(acc, m, sel, 0x90);
 }
 
+// Adds 1 to counter[d] for every active lane.  When every active lane holds
+// the same d (skewed or presorted keys), one lane adds the lane count instead:
+// LDS atomics of many lanes on one word are executed one after another.
+__device__ __forceinline__ void lds_count(uint32_t* counter, uint32_t d)
+{
+    const uint64_t act = ballot(true);
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+    if (ballot(d == d0) == act) {
+        if (lanes_below(act) == 0)
+            atomicAdd(&counter[d0], (uint32_t)__popcll(act));
+    } else {
+        atomicAdd(&counter[d], 1u);
+    }
+}
+
 // Returns x unchanged, but only once y has been computed: an empty asm that
 // claims to read y and rewrite x, to order otherwise independent work.
 __device__ __forceinline__ uint32_t after(uint32_t x, uint32_t y)

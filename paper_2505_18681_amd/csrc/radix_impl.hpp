@@ -46,7 +46,7 @@ __global__ __launch_bounds__(THREADS) void radix_histogram_kernel(const typename
     auto count = [&](U k) {
         const U u = om.to_order(k);
         for (int p = 0; p < passes; ++p)
-            atomicAdd(&mine[p * bins + (int)((u >> ((pass0 + p) * bits)) & mask)], 1u);
+            lds_count(mine + p * bins, (uint32_t)((u >> ((pass0 + p) * bits)) & mask));
     };
 
     constexpr int VEC = 16 / KB;  // keys per 16-byte load
@@ -313,8 +313,9 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
     // back: the bits are exactly the lanes of this item holding the same
     // digit (OR is order-independent, and one wave's LDS instructions run in
     // program order).  Each lane also reads the wave's running count for its
-    // digit; the lowest lane of the group then clears the bucket and adds the
-    // group size to the count.
+    // digit; the lowest lane of the group then clears the bucket (a no-op when
+    // the wave took the one-digit shortcut) and adds the group size to the
+    // count.
     //   rk = digit << 16 | rank of the key among the wave's equal digits
     uint32_t* wh = s_whist + w * BINS;
     uint32_t rk[ITEMS];
@@ -324,10 +325,18 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t d = (uint32_t)((om.to_order(k[i]) >> a.shift) & (U)(BINS - 1));
             const bool valid = item_valid(i);
-            // each lane sets its bit in the 32-bit half of the bucket that holds it
-            if (FULL || valid)
-                atomicOr(reinterpret_cast<uint32_t*>(&bkt[d]) + (lane >> 5), 1u << (lane & 31));
-            const uint64_t peers = bkt[d];
+            uint64_t peers;
+            if (ballot(d == __builtin_amdgcn_readfirstlane(d)) == ~0ull) {
+                // one digit in the whole wave (skewed or presorted keys): the
+                // peers are the valid lanes, and no lane touches the bucket,
+                // whose atomics would otherwise be executed one lane at a time
+                peers = FULL ? ~0ull : ballot(valid);
+            } else {
+                // each lane sets its bit in the 32-bit half of the bucket that holds it
+                if (FULL || valid)
+                    atomicOr(reinterpret_cast<uint32_t*>(&bkt[d]) + (lane >> 5), 1u << (lane & 31));
+                peers = bkt[d];
+            }
             const uint32_t old = wh[d];
             const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));

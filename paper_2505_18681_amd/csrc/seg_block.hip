@@ -109,9 +109,14 @@ __device__ __forceinline__ void sort_segment(const SegBlockArgs& a, const OrderM
             if (wave_base + (uint32_t)(i * kWave) < len) {  // uniform across the wave
                 const uint32_t d = (uint32_t)((om.to_order(k[i]) >> shift) & (U)(BINS - 1));
                 const bool valid = off0 + (uint32_t)(i * kWave) < len;
-                if (valid)
-                    atomicOr(reinterpret_cast<unsigned long long*>(&bkt[d]), (unsigned long long)my_bit);
-                const uint64_t peers = bkt[d];
+                uint64_t peers;
+                if (ballot(d == __builtin_amdgcn_readfirstlane(d)) == ~0ull) {
+                    peers = ballot(valid);  // one digit in the wave: no bucket atomics
+                } else {
+                    if (valid)
+                        atomicOr(reinterpret_cast<unsigned long long*>(&bkt[d]), (unsigned long long)my_bit);
+                    peers = bkt[d];
+                }
                 const uint32_t old = wh[d];
                 const uint32_t below = lanes_below(peers);
                 if (valid && below == 0) {

@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_histogram_kernel(SegHistArgs 
         const U u = om.to_order(k);
 #pragma unroll
         for (int p = 0; p < PASSES; ++p)
-            atomicAdd(&mine[p * kSegBins + (int)((u >> (p * kSegBits)) & (U)(kSegBins - 1))], 1u);
+            lds_count(mine + p * kSegBins, (uint32_t)((u >> (p * kSegBits)) & (U)(kSegBins - 1)));
     };
 
     zero();

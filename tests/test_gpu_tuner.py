@@ -1,0 +1,61 @@
+"""GA autotuner on the GPU: every candidate the search times sorts to the same bytes, and the tuned
+parameters sort every distribution exactly as the oracle does (Sec. 3.2, Algorithm 2; Algorithm 1's
+check of the tuned sort against a reference)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import assert_bits_equal, require_gpu, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dist", ["uniform", "sorted", "distinct16", "zipf"])
+def test_tuned_sort_matches_oracle(dist):
+    es = require_gpu()
+    from paper_2505_18681_amd import tuner
+
+    n = 300_000
+    keys = workloads.make(dist, np.int32, n, 42)
+    want = keys[oracle.stable_perm(keys)]
+    entry = tuner.tune_sort(es, to_dev(keys), seed=1, pop_size=6, generations=3, reps=1)
+    assert entry["evaluations"] >= 6 and len(entry["history"]) == 3
+    best = [h["best"] for h in entry["history"]]
+    assert all(b2 <= b1 for b1, b2 in zip(best, best[1:]))
+    d = dict(entry["params"])
+    d["shape"] = tuple(d["shape"])
+    got = to_np(es.sort(to_dev(keys), params=tuner.to_params(es, d)))
+    assert_bits_equal(got, want, f"tuned sort {dist} {entry['params']}")
+
+
+def test_every_candidate_gives_the_same_bytes():
+    """The fitness function compares each candidate's output with the first one's; a random
+    population over all genes (both routines, every digit width, shapes, thresholds) must pass."""
+    es = require_gpu()
+    from paper_2505_18681_amd import tuner
+
+    keys = workloads.make("gaussian", np.int64, 200_000, 3)
+    dk = to_dev(keys)
+    fit = tuner.SortFitness(es, dk, reps=1)
+    space = tuner.sort_space()
+    repair = tuner.sort_repair(es, es.OP_SORT, es.INT64, keys.size)
+    rng = np.random.default_rng(11)
+    for _ in range(24):
+        fit(repair(space.random(rng, initial=False)))
+    assert_bits_equal(to_np(fit.out), keys[oracle.stable_perm(keys)], "last candidate")
+
+
+def test_tuned_segmented_matches_oracle():
+    es = require_gpu()
+    from paper_2505_18681_amd import tuner
+
+    sizes = workloads.segment_sizes(3000, 5, median=300.0, sigma=2.0, lo=1, hi=200_000)
+    offs = workloads.segment_offsets(sizes)
+    keys = workloads.uniform(np.uint32, int(offs[-1]), 5)
+    entry = tuner.tune_segmented(es, to_dev(keys), to_dev(offs), seed=2, pop_size=6, generations=2, reps=1)
+    d = dict(entry["params"])
+    d["shape"] = tuple(d["shape"])
+    p = tuner.to_params(es, d)
+    got = to_np(es.segmented_sort(to_dev(keys), to_dev(offs), params=p))
+    assert_bits_equal(got, oracle.segmented_sort(keys, offs), f"tuned segmented {entry['params']}")

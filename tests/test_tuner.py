@@ -1,0 +1,161 @@
+"""GA autotuner (Sec. 3.2, Algorithm 2) on the host: operators, schedule, elitism, search quality.
+
+The fitness functions here are synthetic (no GPU): a separable cost with a
+known optimum, so that a plausible mistake in selection, crossover, mutation
+or elitism shows up as a worse result or a broken invariant.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2505_18681_amd import tuner
+
+
+def synthetic_cost(d: dict) -> float:
+    # optimum: algo 4, T_ins 300, T_numpy 50000, d = 8, shape (512, 24)
+    return (5.0 * (d["algo"] != 4) + abs(math.log2(d["insertion_threshold"]) - math.log2(300))
+            + abs(d["fallback_threshold"] - 50000) / 20000.0 + 1.0 * (d["digit_bits"] != 8)
+            + 1.0 * (tuple(d["shape"]) != (512, 24)))
+
+
+def run_synthetic(seed=42, **kw):
+    space = tuner.sort_space()
+    calls = []
+
+    def f(ind):
+        calls.append(ind)
+        return synthetic_cost(space.as_dict(ind))
+
+    return tuner.run_ga(space, f, seed=seed, **kw), calls, space
+
+
+def test_schedule_is_the_papers():
+    """Algorithm 2: 30 individuals, generations 0..9; Sec. 3.2: crossover 0.7, mutation 0.3."""
+    assert (tuner.POP_SIZE, tuner.GENERATIONS, tuner.P_CROSSOVER, tuner.P_MUTATION) == (30, 10, 0.7, 0.3)
+    res, calls, _ = run_synthetic()
+    assert [h["generation"] for h in res.history] == list(range(10))
+    assert res.evaluations == len(calls) == len(set(calls))  # each distinct individual timed once
+
+
+def test_initial_and_full_bounds():
+    """Generation 0 draws T_ins in [2, 256] and T_numpy in [30000, 100000]; later draws use [2, 2048], [1000, 100000]."""
+    space = tuner.sort_space()
+    rng = np.random.default_rng(0)
+    init = [space.as_dict(space.random(rng, initial=True)) for _ in range(2000)]
+    full = [space.as_dict(space.random(rng, initial=False)) for _ in range(2000)]
+    assert min(d["insertion_threshold"] for d in init) >= 2 and max(d["insertion_threshold"] for d in init) <= 256
+    assert min(d["fallback_threshold"] for d in init) >= 30000
+    assert max(d["fallback_threshold"] for d in init) <= 100000
+    assert max(d["insertion_threshold"] for d in full) > 256  # the wider bounds are used
+    assert min(d["fallback_threshold"] for d in full) < 30000
+    assert all(space.contains(space.random(rng, initial=False)) for _ in range(500))
+    assert {d["algo"] for d in init} == {3, 4}
+
+
+def test_elitism_keeps_the_best():
+    res, _, _ = run_synthetic()
+    best = [h["best"] for h in res.history]
+    assert all(b2 <= b1 for b1, b2 in zip(best, best[1:])), best
+    assert res.best_fitness == best[-1]
+
+
+def test_search_finds_the_optimum_region():
+    res, _, space = run_synthetic()
+    d = res.best_dict()
+    assert d["algo"] == 4 and d["digit_bits"] == 8 and tuple(d["shape"]) == (512, 24)
+    assert res.best_fitness < 1.0
+    # better than the best of generation 0 and far better than its mean
+    assert res.best_fitness < res.history[0]["best"] and res.best_fitness < 0.25 * res.history[0]["mean"]
+
+
+def test_ga_beats_random_search_of_equal_budget():
+    res, calls, space = run_synthetic(seed=7)
+    rng = np.random.default_rng(7)
+    rand = min(synthetic_cost(space.as_dict(space.random(rng, initial=False))) for _ in range(len(calls)))
+    assert res.best_fitness <= rand
+
+
+def test_deterministic_for_a_seed():
+    a, _, _ = run_synthetic(seed=3)
+    b, _, _ = run_synthetic(seed=3)
+    c, _, _ = run_synthetic(seed=4)
+    assert a.best == b.best and a.history == b.history
+    assert a.history != c.history
+
+
+def test_uniform_crossover_keeps_genes_in_place():
+    rng = np.random.default_rng(1)
+    a, b = (1, 2, 3, 4, 5), (10, 20, 30, 40, 50)
+    swaps = 0
+    for _ in range(200):
+        c, d = tuner.uniform_crossover(a, b, rng)
+        for i in range(5):
+            assert {c[i], d[i]} == {a[i], b[i]}
+        swaps += sum(ci != ai for ci, ai in zip(c, a))
+    assert 350 < swaps < 650  # about half of 1000 positions
+
+
+def test_uniform_mutation_rate_and_bounds():
+    space = tuner.sort_space()
+    rng = np.random.default_rng(2)
+    ind = (4, 300, 50000, 8, (512, 24))
+    assert tuner.uniform_mutation(ind, space, rng, 0.0) == ind
+    changed = 0
+    for _ in range(400):
+        m = tuner.uniform_mutation(ind, space, rng, 0.3)
+        assert space.contains(m)
+        changed += sum(x != y for x, y in zip(m, ind))
+    # 0.3 per gene, minus redraws that land on the same value (choices of 2..12 options)
+    assert 300 < changed < 640
+
+
+def test_tournament_prefers_fitter():
+    rng = np.random.default_rng(3)
+    pop = [(i,) for i in range(30)]
+    fit = {p: float(p[0]) for p in pop}
+    picks = [tuner.tournament(pop, fit, rng, 3)[0] for _ in range(3000)]
+    assert np.mean(picks) < 10  # size-3 tournaments: expected rank about 7 of 30
+    assert min(picks) == 0
+
+
+def test_seed_individual_survives_when_best():
+    space = tuner.sort_space()
+    opt = (4, 300, 50000, 8, (512, 24))
+    res = tuner.run_ga(space, lambda ind: synthetic_cost(space.as_dict(ind)), seed=1, pop_size=8, generations=3,
+                       seed_individuals=[opt])
+    assert res.best == opt and res.best_fitness == 0.0
+
+
+def test_repair_through_the_library_plan():
+    """Shapes not compiled at a digit width fall back to the default shape (host-only plan call)."""
+    es = pytest.importorskip("paper_2505_18681_amd")
+    repair = tuner.sort_repair(es, es.OP_SORT, es.INT32, 10 ** 6)
+    space = tuner.sort_space()
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        ind = repair(space.random(rng, initial=False))
+        es.plan(es.OP_SORT, es.INT32, 10 ** 6, 0, tuner.to_params(es, space.as_dict(ind)))  # raises if invalid
+    # an alternative shape exists only at 8-bit digits
+    fixed = space.as_dict(repair((4, 8, 50000, 11, (256, 48))))
+    assert fixed["digit_bits"] == 11 and tuple(fixed["shape"]) == (0, 0)
+
+
+def test_params_for_picks_the_nearest_size_class():
+    es = pytest.importorskip("paper_2505_18681_amd")
+    table = {"entries": [
+        {"dtype": "int32", "dist": "uniform", "n": 10 ** 6, "params": {"algo": 4, "digit_bits": 8,
+                                                                        "shape": [512, 16]}},
+        {"dtype": "int32", "dist": "uniform", "n": 10 ** 8, "params": {"algo": 4, "digit_bits": 8,
+                                                                        "shape": [512, 24]}},
+        {"dtype": "int32", "dist": "sorted", "n": 10 ** 8, "params": {"algo": 3, "insertion_threshold": 64}},
+    ]}
+    p = tuner.params_for(es, table, "int32", 3 * 10 ** 7)
+    assert (p.block_threads, p.items_per_thread) == (512, 24)
+    p = tuner.params_for(es, table, "int32", 2 * 10 ** 6)
+    assert (p.block_threads, p.items_per_thread) == (512, 16)
+    p = tuner.params_for(es, table, "int32", 10 ** 8, "sorted")
+    assert p.algo == 3 and p.insertion_threshold == 64
+    p = tuner.params_for(es, table, "int64", 10 ** 8)
+    d = es.default_params()
+    assert (p.algo, p.digit_bits) == (d.algo, d.digit_bits)
