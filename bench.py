@@ -22,7 +22,11 @@ Prints one JSON line with the contract fields plus:
                 call, by its HIP-graph replay and by one plain sort per array
                 (unless --no-batched);
   tuned         GA-tuned parameters per distribution of the 1e8 int32 sweep
-                against the defaults (unless --no-tuned).
+                against the defaults (unless --no-tuned);
+  serving       the request loop under Poisson arrivals (2000/s, log-uniform
+                sizes in [1e3, 1e8], int32/int64/float32, 200 GB budget):
+                p50/p99 latency and keys/s, beside a plain one-call-at-a-time
+                FIFO on the same trace (unless --no-serving).
 """
 from __future__ import annotations
 
@@ -277,6 +281,118 @@ def run_tuned_bench(es, torch, n: int, seed: int, pop: int, generations: int, re
             "entries": out, "search_s": round(time.perf_counter() - t0, 1)}
 
 
+def serving_trace(count: int, rate: float, seed: int, lo: float = 1e3, hi: float = 1e8):
+    """Request trace: Poisson arrivals at `rate` per second, log-uniform sizes in [lo, hi], dtype uniform over
+    int32, int64, float32; returns (arrival seconds, sizes, dtype names)."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    sizes = np.exp(rng.uniform(np.log(lo), np.log(hi), size=count)).astype(np.int64)
+    dts = np.array(["int32", "int64", "float32"])[rng.integers(3, size=count)]
+    return arrivals, sizes, dts
+
+
+def run_serving_bench(es, torch, count: int, rate: float, budget_gb: float, seed: int, streams: int = 4):
+    """The request loop under a Poisson trace, against a plain FIFO of one sort call at a time.
+
+    Inputs are slices of per-dtype pools of uniform keys resident in HBM (the
+    paper's uniform generator, full range; floats without NaN).  Latency is
+    arrival to completion on the host clock; throughput is total keys over the
+    span from the first arrival to the last completion.
+    """
+    import numpy as np
+
+    import workloads
+
+    arrivals, sizes, dts = serving_trace(count, rate, seed)
+    hi = int(sizes.max())
+    pools = {}
+    for name in ("int32", "int64", "float32"):
+        pools[name] = torch.from_numpy(workloads.uniform(np.dtype(name), hi, seed)).cuda()
+    rng = np.random.default_rng(seed + 1)
+    starts = [int(rng.integers(0, hi - int(n) + 1)) for n in sizes]
+    inputs = [pools[d][s:s + int(n)] for d, s, n in zip(dts, starts, sizes)]
+    torch.cuda.synchronize()
+
+    def pct(lat):
+        return {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
+                "mean": round(float(np.mean(lat)), 3), "max": round(float(np.max(lat)), 3)}
+
+    # --- the server: admission by budget, batching, overlapping streams.
+    # The client releases each result once it is done (after reading its
+    # times), except for a sample kept to compare with the request sorted alone.
+    srv = es.Server(hbm_budget_bytes=int(budget_gb * (1 << 30)), streams=streams, batch_max_keys=65536)
+    sample = set(range(0, count, max(1, count // 16)))
+    times = {}
+    outstanding = []
+
+    def reap(block=False):
+        keep = []
+        for i in outstanding:
+            if block:
+                srv.wait(ids[i])
+            if srv.done(ids[i]):
+                times[i] = srv.times(ids[i])
+                if i not in sample:
+                    srv.release(ids[i])
+            else:
+                keep.append(i)
+        return keep
+
+    ids = []
+    t_base = time.perf_counter() - arrivals[0]
+    for i, x in enumerate(inputs):
+        while time.perf_counter() - t_base < arrivals[i]:
+            pass
+        ids.append(srv.submit(x))
+        outstanding.append(i)
+        if len(outstanding) > 8:
+            outstanding = reap()
+    outstanding = reap(block=True)
+    lat = np.array([times[i][2] - times[i][0] for i in range(count)])
+    queued = np.array([times[i][1] - times[i][0] for i in range(count)])
+    span_s = (max(t[2] for t in times.values()) - min(t[0] for t in times.values())) * 1e-3
+    checked = 0
+    for j in sorted(sample):
+        got = srv.result(ids[j])
+        alone = es.sort(inputs[j])
+        if not torch.equal(got.view(torch.uint8), alone.view(torch.uint8)):
+            raise RuntimeError(f"served request {j} differs from the same request sorted alone")
+        srv.release(ids[j])
+        checked += 1
+    st = srv.stats()
+    srv.close()
+    keys = int(sizes.sum())
+    server = {"latency_ms": pct(lat), "queued_ms": pct(queued), "gkeys_per_s": round(keys / span_s / 1e9, 3),
+              "span_s": round(span_s, 3), "jobs": st["jobs"], "batched_requests": st["batched_requests"],
+              "max_concurrent_jobs": st["max_concurrent_jobs"], "peak_gb": round(st["peak_bytes"] / 2**30, 2),
+              "identical_to_alone": checked}
+
+    # --- plain FIFO: one sort call at a time on one stream, same trace
+    stream = torch.cuda.current_stream()
+    done = []
+    t_base = time.perf_counter() - arrivals[0]
+    outs = {}
+    for i, x in enumerate(inputs):
+        while time.perf_counter() - t_base < arrivals[i]:
+            pass
+        es.sort(x)
+        stream.synchronize()
+        done.append(time.perf_counter() - t_base)
+    lat_plain = (np.array(done) - arrivals) * 1e3
+    span_plain = done[-1] - arrivals[0]
+    plain = {"latency_ms": pct(lat_plain), "gkeys_per_s": round(keys / span_plain / 1e9, 3),
+             "span_s": round(span_plain, 3)}
+    del pools, inputs, outs
+    torch.cuda.empty_cache()
+    return {"workload": f"{count} requests, Poisson arrivals at {rate:.0f}/s, log-uniform sizes in [1e3, 1e8] "
+                        f"({keys} keys), dtype uniform over int32/int64/float32, HBM budget {budget_gb:.0f} GB, "
+                        f"{streams} streams",
+            "value": server["latency_ms"]["p99"], "unit": "ms p99 latency", "server": server,
+            "plain_fifo": plain}
+
+
 def cpu_baseline(dtype_name: str, n_sample: int, seed: int):
     """The oracle, untuned, on a bounded sample of the same workload (one host thread)."""
     import numpy as np
@@ -312,6 +428,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-nseg", type=int, default=100_000)
     ap.add_argument("--no-tuned", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-rate", type=float, default=2000.0)
+    ap.add_argument("--serving-budget-gb", type=float, default=200.0)
     ap.add_argument("--tuned-n", type=int, default=100_000_000)
     ap.add_argument("--tuned-pop", type=int, default=10)
     ap.add_argument("--tuned-generations", type=int, default=4)
@@ -366,6 +486,17 @@ def main():
         print(f"# tuned: {[(e['dist'], e['ms'], e['default_ms']) for e in tuned['entries']]}", file=sys.stderr,
               flush=True)
 
+    serving = None
+    if not args.no_serving:
+        serving = run_serving_bench(es, torch, args.serving_requests, args.serving_rate, args.serving_budget_gb,
+                                    args.seed)
+        # the same request mix offered faster than the GPU sorts it: saturation throughput
+        serving["overload"] = run_serving_bench(es, torch, args.serving_requests, 10 * args.serving_rate,
+                                                args.serving_budget_gb, args.seed + 7)
+        print(f"# serving: server {serving['server']['latency_ms']} {serving['server']['gkeys_per_s']} Gkeys/s; "
+              f"plain {serving['plain_fifo']['latency_ms']} {serving['plain_fifo']['gkeys_per_s']} Gkeys/s",
+              file=sys.stderr, flush=True)
+
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -418,6 +549,7 @@ def main():
         "secondary": secondary,
         "batched": batched,
         "tuned": tuned,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

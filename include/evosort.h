@@ -82,7 +82,9 @@ typedef enum evosort_status {
     EVOSORT_ERR_UNSUPPORTED_PARAM = 3, /* e.g. a tile shape that is not compiled in */
     EVOSORT_ERR_TEMP_TOO_SMALL = 4,    /* temp_bytes below evosort_temp_bytes() */
     EVOSORT_ERR_HIP = 5,               /* a HIP launch or runtime call failed */
-    EVOSORT_ERR_DEVICE_TIMEOUT = 6     /* a kernel's bounded wait ran out (see evosort_check_device_error) */
+    EVOSORT_ERR_DEVICE_TIMEOUT = 6,    /* a kernel's bounded wait ran out (see evosort_check_device_error) */
+    EVOSORT_ERR_OVER_BUDGET = 7,       /* a served request needs more HBM than the server's whole budget */
+    EVOSORT_ERR_PENDING = 8            /* a served request has not finished yet */
 } evosort_status;
 
 /* Operations, for evosort_temp_bytes and evosort_plan. */
@@ -308,6 +310,102 @@ evosort_status evosort_segmented_stats(const void *temp, size_t temp_bytes, uint
 evosort_status evosort_sort_each(int dtype, const void *keys_in, void *keys_out, const void *vals_in,
                                  void *vals_out, uint32_t value_bytes, const int64_t *host_offsets, int64_t nseg,
                                  void *temp, size_t temp_bytes, const evosort_params *p, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: a request loop with continuous batching.                          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * A sort server admits sort requests of any length and key type and runs
+ * them on one GPU while others are still arriving (the paper's adaptive,
+ * drop-in sort offered as a service; Sec. 1 and Sec. 4.3).  It owns one
+ * device arena of hbm_budget_bytes, reserved once at creation: every admitted
+ * request's output and scratch come from it, so the budget bounds the HBM the
+ * server holds at any time.  A scheduler thread:
+ *   - admits waiting requests in arrival order (first in, first out) while a
+ *     stream slot is free and the arena can hold the request's output and
+ *     scratch; a request that does not fit waits for releases (no request
+ *     overtakes an earlier one);
+ *   - packs consecutive waiting requests of one key type that are at most
+ *     batch_max_keys long into one batch: their keys are gathered into one
+ *     arena buffer and sorted by one batched segmented sort, in place;
+ *   - runs each longer request as its own evosort_sort call;
+ *   - runs up to `streams` jobs (batches or single requests) at once, each on
+ *     its own HIP stream, so work admitted at different times overlaps on
+ *     the device, and retires jobs as their streams finish.
+ * Every result is the one evosort_sort gives for that request alone: the
+ * stable sort is unique, whatever the batch or the other work on the GPU.
+ *
+ * Results stay in the arena (device-resident) until evosort_server_release;
+ * a client that never releases stalls admission once the arena is full.
+ */
+typedef struct evosort_server evosort_server;
+
+typedef struct evosort_server_config {
+    uint32_t struct_size;      /* set by evosort_server_default_config */
+    uint32_t streams;          /* concurrent jobs (HIP streams), 1..16; default 4 */
+    uint64_t hbm_budget_bytes; /* arena size in bytes; default 1 GiB */
+    uint64_t batch_max_keys;   /* requests of at most this many keys are batched; 0 = no batching;
+                                  default 65536 */
+    uint32_t batch_max_requests; /* requests per batch, 1..8192; default 2048 */
+    uint32_t reserved;
+    evosort_params params;     /* parameters of every sort the server runs (default params) */
+} evosort_server_config;
+
+typedef struct evosort_server_stats {
+    uint64_t submitted, completed, released, failed;
+    uint64_t jobs;             /* batches and single requests launched */
+    uint64_t batched_requests; /* requests that ran inside a batch */
+    uint64_t keys_completed;
+    uint64_t bytes_in_use;     /* arena bytes held now (running and unreleased results) */
+    uint64_t peak_bytes;       /* most arena bytes held at once */
+    uint64_t budget_bytes;
+    uint32_t max_concurrent_jobs; /* most jobs on the GPU at once */
+    uint32_t waiting;          /* requests not yet admitted */
+} evosort_server_stats;
+
+void evosort_server_default_config(evosort_server_config *cfg);
+
+/* Create a server on the current HIP device.  Reserves the arena (the only
+ * device allocation the server makes), the streams and pinned staging. */
+evosort_status evosort_server_create(const evosort_server_config *cfg, evosort_server **out);
+
+/* Wait for every admitted request, stop the scheduler and free everything.
+ * Results not yet copied out are lost.  Requests still waiting are dropped. */
+evosort_status evosort_server_destroy(evosort_server *srv);
+
+/*
+ * Submit a request: n keys of `dtype` at DEVICE pointer keys_in, which must
+ * stay valid and unchanged until the request completes (it is only read).
+ * Returns at once with *id.  EVOSORT_ERR_OVER_BUDGET if the request could
+ * never fit in the arena.
+ */
+evosort_status evosort_server_submit(evosort_server *srv, int dtype, const void *keys_in, int64_t n, uint64_t *id);
+
+/* Non-blocking: EVOSORT_OK and *keys_out (DEVICE pointer into the arena,
+ * valid until release) once done; EVOSORT_ERR_PENDING while not; the sort's
+ * error status if it failed. */
+evosort_status evosort_server_result(evosort_server *srv, uint64_t id, const void **keys_out);
+
+/* Block until request id is done; then as evosort_server_result. */
+evosort_status evosort_server_wait(evosort_server *srv, uint64_t id, const void **keys_out);
+
+/* Copy a finished result to dst (DEVICE pointer, n keys) on `stream`. */
+evosort_status evosort_server_copy_out(evosort_server *srv, uint64_t id, void *dst, void *stream);
+
+/* Host times of a finished request, in milliseconds since the server was
+ * created: submitted, admitted (launched), finished (its stream observed
+ * done by the scheduler, which polls every few microseconds while busy). */
+evosort_status evosort_server_times(evosort_server *srv, uint64_t id, double *submit_ms, double *admit_ms,
+                                    double *done_ms);
+
+/* Give a finished request's arena memory back (its result pointer dies). */
+evosort_status evosort_server_release(evosort_server *srv, uint64_t id);
+
+/* Block until every submitted request is done. */
+evosort_status evosort_server_drain(evosort_server *srv);
+
+evosort_status evosort_server_get_stats(evosort_server *srv, evosort_server_stats *out);
 
 /* ------------------------------------------------------------------------ */
 /* Errors and measurement.                                                   */

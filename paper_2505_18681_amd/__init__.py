@@ -15,6 +15,8 @@ Public calls (names follow the C ABI):
 * :func:`segmented_sort`, :func:`segmented_sort_pairs` -- a batch of arrays
   (segments of one buffer) in one fixed launch sequence; :func:`sort_each`
   -- the same batch one plain sort per segment; :func:`segmented_stats`;
+* :class:`Server` -- the request loop: admission by an HBM budget,
+  continuous batching of short requests, overlapping jobs on several streams;
 * :func:`plan`, :func:`temp_bytes`, :func:`default_params` -- host-only queries;
 * :func:`profile_enable`, :func:`profile_reset`, :func:`profile_collect` --
   per-kernel HIP-event timing.
@@ -42,8 +44,8 @@ INT32, INT64, UINT32, FLOAT32, FLOAT64 = 1, 2, 3, 4, 5
 ALGO_AUTO, ALGO_MERGE, ALGO_RADIX = 0, 3, 4
 OP_SORT, OP_SORT_PAIRS, OP_ARGSORT = 0, 1, 2
 PATH_NAMES = {0: "copy", 1: "small", 2: "radix", 3: "merge"}
-OK, ERR_INVALID_ARG, ERR_UNSUPPORTED_DTYPE, ERR_UNSUPPORTED_PARAM, ERR_TEMP_TOO_SMALL, ERR_HIP, ERR_DEVICE_TIMEOUT = \
-    range(7)
+(OK, ERR_INVALID_ARG, ERR_UNSUPPORTED_DTYPE, ERR_UNSUPPORTED_PARAM, ERR_TEMP_TOO_SMALL, ERR_HIP, ERR_DEVICE_TIMEOUT,
+ ERR_OVER_BUDGET, ERR_PENDING) = range(9)
 DEBUG_WITHHOLD_TILE0 = 0x1
 
 EXPORTED = (
@@ -53,6 +55,9 @@ EXPORTED = (
     "evosort_profile_enable", "evosort_profile_reset", "evosort_profile_collect", "evosort_profile_get",
     "evosort_segmented_temp_bytes", "evosort_segmented_sort", "evosort_segmented_sort_pairs",
     "evosort_segmented_capacity", "evosort_segmented_stats", "evosort_sort_each",
+    "evosort_server_default_config", "evosort_server_create", "evosort_server_destroy", "evosort_server_submit",
+    "evosort_server_result", "evosort_server_wait", "evosort_server_copy_out", "evosort_server_times",
+    "evosort_server_release", "evosort_server_drain", "evosort_server_get_stats",
 )
 
 
@@ -95,6 +100,29 @@ class PlanInfo(ctypes.Structure):
     ]
 
 
+class ServerConfig(ctypes.Structure):
+    """``evosort_server_config`` (see include/evosort.h)."""
+
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("streams", ctypes.c_uint32),
+        ("hbm_budget_bytes", ctypes.c_uint64),
+        ("batch_max_keys", ctypes.c_uint64),
+        ("batch_max_requests", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("params", Params),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    """``evosort_server_stats`` (see include/evosort.h)."""
+
+    _fields_ = [(name, ctypes.c_uint64) for name in (
+        "submitted", "completed", "released", "failed", "jobs", "batched_requests", "keys_completed",
+        "bytes_in_use", "peak_bytes", "budget_bytes")] + [
+        ("max_concurrent_jobs", ctypes.c_uint32), ("waiting", ctypes.c_uint32)]
+
+
 _vp, _i64, _u32, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int, ctypes.c_size_t
 _P = ctypes.POINTER(Params)
 
@@ -126,6 +154,23 @@ _lib.evosort_segmented_sort_pairs.argtypes = [_i32, _vp, _vp, _vp, _vp, _u32, _i
 _lib.evosort_segmented_capacity.argtypes = [_i32, _u32, ctypes.POINTER(_i64)]
 _lib.evosort_segmented_stats.argtypes = [_vp, _sz, ctypes.POINTER(_u32), ctypes.POINTER(_u32), _vp]
 _lib.evosort_sort_each.argtypes = [_i32, _vp, _vp, _vp, _vp, _u32, ctypes.POINTER(_i64), _i64, _vp, _sz, _P, _vp]
+_SRV = ctypes.c_void_p
+_lib.evosort_server_default_config.argtypes = [ctypes.POINTER(ServerConfig)]
+_lib.evosort_server_default_config.restype = None
+_lib.evosort_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(_SRV)]
+_lib.evosort_server_destroy.argtypes = [_SRV]
+_lib.evosort_server_submit.argtypes = [_SRV, _i32, _vp, _i64, ctypes.POINTER(ctypes.c_uint64)]
+_lib.evosort_server_result.argtypes = [_SRV, ctypes.c_uint64, ctypes.POINTER(_vp)]
+_lib.evosort_server_wait.argtypes = [_SRV, ctypes.c_uint64, ctypes.POINTER(_vp)]
+_lib.evosort_server_copy_out.argtypes = [_SRV, ctypes.c_uint64, _vp, _vp]
+_lib.evosort_server_times.argtypes = [_SRV, ctypes.c_uint64] + [ctypes.POINTER(ctypes.c_double)] * 3
+_lib.evosort_server_release.argtypes = [_SRV, ctypes.c_uint64]
+_lib.evosort_server_drain.argtypes = [_SRV]
+_lib.evosort_server_get_stats.argtypes = [_SRV, ctypes.POINTER(ServerStats)]
+for _f in ("evosort_server_create", "evosort_server_destroy", "evosort_server_submit", "evosort_server_result",
+           "evosort_server_wait", "evosort_server_copy_out", "evosort_server_times", "evosort_server_release",
+           "evosort_server_drain", "evosort_server_get_stats"):
+    getattr(_lib, _f).restype = ctypes.c_int
 for _f in ("evosort_segmented_temp_bytes", "evosort_segmented_sort", "evosort_segmented_sort_pairs",
            "evosort_segmented_capacity", "evosort_segmented_stats", "evosort_sort_each"):
     getattr(_lib, _f).restype = ctypes.c_int
@@ -485,6 +530,112 @@ def check_device_error(temp, *, stream=None) -> int:
     torch = _torch()
     with torch.cuda.device(temp.device):
         return _lib.evosort_check_device_error(_ptr(temp), temp.numel(), _stream(temp.device, stream))
+
+
+# ------------------------------------------------------------------ serving --
+def server_default_config(**overrides) -> ServerConfig:
+    """``evosort_server_default_config`` with keyword overrides (``params`` takes a :class:`Params`)."""
+    c = ServerConfig()
+    _lib.evosort_server_default_config(ctypes.byref(c))
+    for k, v in overrides.items():
+        if not hasattr(c, k):
+            raise AttributeError(f"evosort_server_config has no field {k!r}")
+        setattr(c, k, v)
+    return c
+
+
+class Server:
+    """A sort server on the current device (``evosort_server_*``).
+
+    ``submit`` takes a device tensor of keys (kept alive by the server object
+    until the request is released) and returns a request id; ``wait`` /
+    ``done`` report completion; ``result`` copies the sorted keys into a new
+    tensor on PyTorch's current stream; ``release`` frees the request's HBM.
+    """
+
+    def __init__(self, *, hbm_budget_bytes: int = 1 << 30, streams: int = 4, batch_max_keys: int = 65536,
+                 batch_max_requests: int = 2048, params: Params | None = None, device=None):
+        torch = _torch()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        cfg = server_default_config(hbm_budget_bytes=int(hbm_budget_bytes), streams=int(streams),
+                                    batch_max_keys=int(batch_max_keys), batch_max_requests=int(batch_max_requests))
+        if params is not None:
+            cfg.params = params
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check("evosort_server_create", _lib.evosort_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self._inputs = {}
+
+    def close(self):
+        if self._h:
+            _check("evosort_server_destroy", _lib.evosort_server_destroy(self._h))
+            self._h = ctypes.c_void_p()
+            self._inputs.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, keys) -> int:
+        keys = _key_tensor(keys)
+        if keys.device != self.device:
+            raise ValueError(f"keys must be on {self.device}")
+        rid = ctypes.c_uint64(0)
+        # the keys must be in HBM before the server's streams read them
+        _torch().cuda.current_stream(self.device).synchronize()
+        _check("evosort_server_submit", _lib.evosort_server_submit(self._h, dtype_code(keys.dtype), _ptr(keys),
+                                                                   keys.numel(), ctypes.byref(rid)))
+        self._inputs[rid.value] = keys
+        return rid.value
+
+    def done(self, rid: int) -> bool:
+        st = _lib.evosort_server_result(self._h, rid, None)
+        if st == ERR_PENDING:
+            return False
+        _check("evosort_server_result", st)
+        return True
+
+    def wait(self, rid: int):
+        _check("evosort_server_wait", _lib.evosort_server_wait(self._h, rid, None))
+
+    def result(self, rid: int, out=None):
+        """The sorted keys of a finished request, copied into ``out`` (or a new tensor)."""
+        torch = _torch()
+        keys = self._inputs[rid]
+        out = torch.empty_like(keys) if out is None else out
+        if out.numel() != keys.numel() or out.dtype != keys.dtype:
+            raise ValueError("out must match the request's keys")
+        self.wait(rid)
+        _check("evosort_server_copy_out",
+               _lib.evosort_server_copy_out(self._h, rid, _ptr(out), _stream(self.device, None)))
+        return out
+
+    def times(self, rid: int) -> tuple:
+        """(submitted, admitted, finished) in ms since the server was created."""
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check("evosort_server_times", _lib.evosort_server_times(self._h, rid, ctypes.byref(a), ctypes.byref(b),
+                                                                 ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def release(self, rid: int):
+        _check("evosort_server_release", _lib.evosort_server_release(self._h, rid))
+        self._inputs.pop(rid, None)
+
+    def drain(self):
+        _check("evosort_server_drain", _lib.evosort_server_drain(self._h))
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check("evosort_server_get_stats", _lib.evosort_server_get_stats(self._h, ctypes.byref(s)))
+        return {name: int(getattr(s, name)) for name, _ in ServerStats._fields_}
 
 
 # --------------------------------------------------------------- profiling --

@@ -1133,6 +1133,10 @@ const char* evosort_status_string(int status)
         return "HIP error (see evosort_last_hip_error)";
     case EVOSORT_ERR_DEVICE_TIMEOUT:
         return "a device-side wait ran out of its spin limit";
+    case EVOSORT_ERR_OVER_BUDGET:
+        return "request needs more HBM than the server's whole budget";
+    case EVOSORT_ERR_PENDING:
+        return "request not finished yet";
     default:
         return "unknown status";
     }

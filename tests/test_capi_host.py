@@ -238,3 +238,26 @@ def test_segmented_plan_and_argument_errors():
     offs = (ctypes.c_int64 * 3)(0, 10, 5)
     assert lib.evosort_sort_each(es.UINT32, FAKE, FAKE + big, None, None, 0, offs, 2, FAKE + 2 * big, big, None,
                                  None) == es.ERR_INVALID_ARG
+
+
+def test_server_config_defaults_and_validation():
+    """The server's config checks run on the host before any device call."""
+    import ctypes
+
+    import paper_2505_18681_amd as es
+
+    c = es.server_default_config()
+    assert c.struct_size == ctypes.sizeof(es.ServerConfig)
+    assert (c.streams, c.hbm_budget_bytes, c.batch_max_keys, c.batch_max_requests) == (4, 1 << 30, 65536, 2048)
+    assert c.params.digit_bits == 8
+    h = ctypes.c_void_p()
+    for bad in (dict(streams=0), dict(streams=17), dict(batch_max_requests=0), dict(batch_max_requests=9000),
+                dict(hbm_budget_bytes=4096), dict(batch_max_keys=1 << 30)):
+        cfg = es.server_default_config(**bad)
+        assert es._lib.evosort_server_create(ctypes.byref(cfg), ctypes.byref(h)) == es.ERR_INVALID_ARG, bad
+    cfg = es.server_default_config()
+    cfg.struct_size = 8
+    assert es._lib.evosort_server_create(ctypes.byref(cfg), ctypes.byref(h)) == es.ERR_INVALID_ARG
+    assert es._lib.evosort_server_submit(None, es.INT32, None, 0, None) == es.ERR_INVALID_ARG
+    assert es.status_string(es.ERR_OVER_BUDGET).startswith("request")
+    assert es.status_string(es.ERR_PENDING).startswith("request")
