@@ -71,18 +71,32 @@ __device__ __forceinline__ uint32_t keep_equal_bits(uint32_t acc, uint32_t m, ui
     return __builtin_amdgcn_bitop3_b32(acc, m, sel, 0x90);
 }
 
-// Adds 1 to counter[d] for every active lane.  When every active lane holds
-// the same d (skewed or presorted keys), one lane adds the lane count instead:
-// LDS atomics of many lanes on one word are executed one after another.
-__device__ __forceinline__ void lds_count(uint32_t* counter, uint32_t d)
+// Counts one key per active lane into the digit histograms of several
+// passes: hist[p * bins + digit_p] for p = passes - 1 down to 0, where
+// digit_p(p) gives this lane's digit of pass p.  While every active lane
+// holds the same digit (skewed or presorted keys, most significant digits
+// first), one lane adds the lane count: LDS atomics of many lanes on one
+// word are executed one after another.  From the first pass whose digits
+// differ, every lane adds 1 (random keys take that path at once, after one
+// test).
+template <class DigitOf>
+__device__ __forceinline__ void lds_count_passes(uint32_t* hist, int bins, int passes, DigitOf&& digit_p)
 {
     const uint64_t act = ballot(true);
-    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-    if (ballot(d == d0) == act) {
-        if (lanes_below(act) == 0)
-            atomicAdd(&counter[d0], (uint32_t)__popcll(act));
-    } else {
-        atomicAdd(&counter[d], 1u);
+    bool same = true;
+#pragma unroll
+    for (int p = passes - 1; p >= 0; --p) {
+        const uint32_t d = digit_p(p);
+        if (same) {
+            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+            if (ballot(d == d0) == act) {
+                if (lanes_below(act) == 0)
+                    atomicAdd(&hist[p * bins + (int)d0], (uint32_t)__popcll(act));
+                continue;
+            }
+            same = false;
+        }
+        atomicAdd(&hist[p * bins + (int)d], 1u);
     }
 }
 

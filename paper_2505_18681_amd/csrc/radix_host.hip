@@ -48,6 +48,25 @@ hipError_t launch_radix_histogram(const KeyDesc& kd, const void* keys, int64_t n
     // that each group has at least one private copy; add copies (at most one
     // per wave) while they fit.
     const size_t per_pass = ((size_t)1 << bits) * 4;
+    if (bits == 8 && (passes == 4 || passes == 8)) {
+        // every pass in one launch, one private copy per wave
+        const int grid = histogram_grid(n);
+        const int copies = kHistThreads / kWave;
+        const size_t lds = (size_t)copies * passes * per_pass;
+        auto* h = reinterpret_cast<unsigned long long*>(hist);
+        if (kd.bytes == 4 && passes == 4) {
+            OrderMap<uint32_t> om{(uint32_t)kd.flip, (uint32_t)kd.neg};
+            hipLaunchKernelGGL((radix_histogram8_kernel<4, kHistThreads, 4>), dim3(grid), dim3(kHistThreads), lds,
+                               s, reinterpret_cast<const uint32_t*>(keys), n, om, copies, h);
+            return hipGetLastError();
+        }
+        if (kd.bytes == 8 && passes == 8) {
+            OrderMap<uint64_t> om{kd.flip, kd.neg};
+            hipLaunchKernelGGL((radix_histogram8_kernel<8, kHistThreads, 8>), dim3(grid), dim3(kHistThreads), lds,
+                               s, reinterpret_cast<const uint64_t*>(keys), n, om, copies, h);
+            return hipGetLastError();
+        }
+    }
     const int group = (int)((64 * 1024) / per_pass) < passes ? (int)((64 * 1024) / per_pass) : passes;
     const int grid = histogram_grid(n);
     auto* h = reinterpret_cast<unsigned long long*>(hist);

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(THREADS) void radix_histogram_kernel(const typename
     auto count = [&](U k) {
         const U u = om.to_order(k);
         for (int p = 0; p < passes; ++p)
-            lds_count(mine + p * bins, (uint32_t)((u >> ((pass0 + p) * bits)) & mask));
+            atomicAdd(&mine[p * bins + (int)((u >> ((pass0 + p) * bits)) & mask)], 1u);
     };
 
     constexpr int VEC = 16 / KB;  // keys per 16-byte load
@@ -93,6 +93,75 @@ __global__ __launch_bounds__(THREADS) void radix_histogram_kernel(const typename
             s += lds_hist[c * per_copy + i];
         if (s)
             atomicAdd(&hist[(size_t)pass0 * bins + i], (unsigned long long)s);
+    }
+}
+
+// The same for 8-bit digits and all passes in one launch (the common case),
+// with the pass count known at compile time.  Skewed and presorted keys:
+// lds_count_passes lets one lane count a whole wave while its digits agree,
+// most significant digit first.
+template <int KB, int THREADS, int PASSES>
+__global__ __launch_bounds__(THREADS) void radix_histogram8_kernel(const typename KeyWord<KB>::U* __restrict__ keys,
+                                                                   int64_t n, OrderMap<typename KeyWord<KB>::U> om,
+                                                                   int copies, unsigned long long* __restrict__ hist)
+{
+    using U = typename KeyWord<KB>::U;
+    constexpr int BINS = 256;
+    constexpr int PER_COPY = PASSES * BINS;
+    extern __shared__ uint32_t lds_hist[];
+    for (int i = threadIdx.x; i < copies * PER_COPY; i += THREADS)
+        lds_hist[i] = 0;
+    __syncthreads();
+
+    uint32_t* mine = lds_hist + (int)((threadIdx.x / kWave) % copies) * PER_COPY;
+    auto count = [&](U k) {
+        const U u = om.to_order(k);
+        lds_count_passes(mine, BINS, PASSES, [&](int p) { return (uint32_t)(u >> (8 * p)) & 0xffu; });
+    };
+
+    constexpr int VEC = 16 / KB;
+    constexpr int UNROLL = 4;
+    const int64_t stride = (int64_t)gridDim.x * THREADS;
+    const int64_t gtid = (int64_t)blockIdx.x * THREADS + threadIdx.x;
+    int64_t done = 0;
+    if ((reinterpret_cast<uintptr_t>(keys) & 15) == 0) {
+        const int64_t nvec = n / VEC;
+        const uint4* kv = reinterpret_cast<const uint4*>(keys);
+        int64_t v = gtid;
+        for (; v + (UNROLL - 1) * stride < nvec; v += UNROLL * stride) {
+            uint4 w[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u)
+                w[u] = kv[v + u * stride];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                U k[VEC];
+                __builtin_memcpy(k, &w[u], 16);
+#pragma unroll
+                for (int j = 0; j < VEC; ++j)
+                    count(k[j]);
+            }
+        }
+        for (; v < nvec; v += stride) {
+            uint4 w = kv[v];
+            U k[VEC];
+            __builtin_memcpy(k, &w, 16);
+#pragma unroll
+            for (int j = 0; j < VEC; ++j)
+                count(k[j]);
+        }
+        done = nvec * VEC;
+    }
+    for (int64_t i = done + gtid; i < n; i += stride)
+        count(keys[i]);
+    __syncthreads();
+
+    for (int i = threadIdx.x; i < PER_COPY; i += THREADS) {
+        uint32_t s = 0;
+        for (int c = 0; c < copies; ++c)
+            s += lds_hist[c * PER_COPY + i];
+        if (s)
+            atomicAdd(&hist[i], (unsigned long long)s);
     }
 }
 
@@ -270,7 +339,10 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
     // Offsets inside the tile are 32-bit; only the tile base is 64-bit.
     const uint32_t off0 = (uint32_t)(w * WAVE_KEYS + lane);
     const U* __restrict__ tile_keys = reinterpret_cast<const U*>(a.keys_in) + tile_start;
-    auto item_valid = [&](int i) { return FULL || off0 + (uint32_t)(i * kWave) < nvalid; };
+    // item i of this thread is valid iff i * 64 < rem: one register for all
+    // items instead of one offset per item
+    const int32_t rem = FULL ? 0 : (int32_t)materialize(nvalid - off0);
+    auto item_valid = [&](int i) { return FULL || (int32_t)(i * kWave) < rem; };
 
     // ---- load ----------------------------------------------------------
     // Past the end of the last tile the load is clamped to the last key (in
@@ -316,9 +388,16 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
     // digit; the lowest lane of the group then clears the bucket (a no-op when
     // the wave took the one-digit shortcut) and adds the group size to the
     // count.
-    //   rk = digit << 16 | rank of the key among the wave's equal digits
+    // rk holds each key's rank among the wave's equal digits, 16 bits per
+    // key, two keys per word (the digit is recomputed from the key later):
+    // fewer live registers, so more workgroups fit on a CU.
     uint32_t* wh = s_whist + w * BINS;
-    uint32_t rk[ITEMS];
+    constexpr int PAIRS = (ITEMS + 1) / 2;
+    uint32_t rk[PAIRS];
+    auto put_rank = [&](int i, uint32_t r) {
+        // materialized now: a deferred pack would keep its operands alive
+        rk[i >> 1] = (i & 1) ? materialize(rk[i >> 1] | (r << 16)) : materialize(r);
+    };
     if constexpr (Lds::kBuckets) {
         uint64_t* bkt = reinterpret_cast<uint64_t*>(L.uni + Lds::BUCKET_OFFSET) + w * BINS;
 #pragma unroll
@@ -344,9 +423,7 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
                 bkt[d] = 0;
                 wh[d] = old + (uint32_t)__popcll(peers);
             }
-            // packed now: a deferred pack would keep d, old and below
-            // alive per item (three registers instead of one)
-            rk[i] = materialize((d << 16) | (old + below));
+            put_rank(i, old + below);
         }
     } else {
         // Wide digits (the buckets would not fit in LDS): the same peer mask
@@ -358,7 +435,7 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
             // Item i's ballots start after item i-1's result: otherwise the
             // compiler hoists every item's 64-bit ballots and spills them.
             if (i > 0)
-                d = after(d, rk[i - 1]);
+                d = after(d, rk[(i - 1) >> 1]);
             const bool valid = item_valid(i);
             const uint64_t vmask = FULL ? ~0ull : ballot(valid);
             uint32_t plo = (uint32_t)vmask, phi = (uint32_t)(vmask >> 32);
@@ -373,9 +450,7 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
             const uint32_t old = wh[d];
             if ((FULL || valid) && below == 0)
                 wh[d] = old + (uint32_t)(__builtin_popcount(plo) + __builtin_popcount(phi));
-            // packed now: a deferred pack would keep d, old and below
-            // alive per item (three registers instead of one)
-            rk[i] = materialize((d << 16) | (old + below));
+            put_rank(i, old + below);
         }
     }
     __syncthreads();
@@ -434,16 +509,31 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
 
     // ---- local positions, then stage the tile in digit order ----------------
     // Done before the look-back so that predecessors get more time to publish.
+    // Positions in the tile are below 2^16 and replace the ranks in place,
+    // two per word; 0xffff marks an item past the end of the last tile.
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i)
-        rk[i] = item_valid(i) ? s_whist[w * BINS + (rk[i] >> 16)] + (rk[i] & 0xffffu) : 0xffffffffu;
+    for (int j = 0; j < PAIRS; ++j) {
+        uint32_t packed = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = 2 * j + h;
+            if (i < ITEMS) {
+                const uint32_t d = (uint32_t)((om.to_order(k[i]) >> a.shift) & (U)(BINS - 1));
+                const uint32_t pos =
+                    item_valid(i) ? s_whist[w * BINS + d] + ((rk[j] >> (16 * h)) & 0xffffu) : 0xffffu;
+                packed |= pos << (16 * h);
+            }
+        }
+        rk[j] = materialize(packed);
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        if (FULL || rk[i] != 0xffffffffu) {
-            s_keys[rk[i]] = k[i];
+        const uint32_t pos = (rk[i >> 1] >> (16 * (i & 1))) & 0xffffu;
+        if (FULL || pos != 0xffffu) {
+            s_keys[pos] = k[i];
             if constexpr (VB != 0)
-                s_vals[rk[i]] = v[i];
+                s_vals[pos] = v[i];
         }
     }
 
@@ -510,7 +600,7 @@ __global__ __launch_bounds__(THREADS) void radix_pass_kernel(RadixPassArgs a, Or
 {
     using Lds = PassLds<KB, VB, BITS, THREADS, ITEMS>;
     constexpr int TILE = THREADS * ITEMS;
-    static_assert(kWave * ITEMS < 65536, "rank field is 16 bits");
+    static_assert(THREADS * ITEMS < 65535, "tile positions are 16 bits");
     static_assert((1 << BITS) <= 4096, "digit field is 12 bits");
     __shared__ Lds L;
 

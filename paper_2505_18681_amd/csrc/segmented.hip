@@ -172,9 +172,8 @@ __global__ __launch_bounds__(kSegThreads) void seg_histogram_kernel(SegHistArgs 
     uint32_t* mine = h[threadIdx.x / kWave];
     auto count_key = [&](U k) {
         const U u = om.to_order(k);
-#pragma unroll
-        for (int p = 0; p < PASSES; ++p)
-            lds_count(mine + p * kSegBins, (uint32_t)((u >> (p * kSegBits)) & (U)(kSegBins - 1)));
+        lds_count_passes(mine, kSegBins, PASSES,
+                         [&](int p) { return (uint32_t)((u >> (p * kSegBits)) & (U)(kSegBins - 1)); });
     };
 
     zero();
