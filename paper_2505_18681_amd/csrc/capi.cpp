@@ -137,7 +137,8 @@ struct Plan {
     uint32_t debug_flags;
     uint32_t t_ins;
     // radix scratch layout (byte offsets into temp)
-    size_t off_keys_a, off_keys_b, off_vals, off_hist, off_bases, off_status, off_ctr, off_err;
+    size_t off_keys_a, off_keys_b, off_vals, off_hist, off_bases, off_status, off_ctr, off_err, off_blocks;
+    bool prefix0;  // pass 0 takes its tile offsets from the histogram's per-tile counts
     size_t zero_begin, zero_end;
     size_t status_pass_bytes;
     // merge scratch layout
@@ -271,6 +272,12 @@ evosort_status make_plan(int op, int dtype, int64_t n, uint32_t value_bytes, con
         P->zero_end = off;
         P->off_bases = off;
         off = align_up(off + (size_t)passes * bins * 8);
+        // 8-bit digits, all passes in one histogram launch: pass 0's tile
+        // offsets come from per-tile counts and an exclusive scan over tiles
+        P->prefix0 = P->bits == 8 && passes == kb && tiles > 0;
+        P->off_blocks = off;
+        if (P->prefix0)
+            off = align_up(off + (size_t)((tiles + kTilePrefixBlock - 1) / kTilePrefixBlock) * 256 * 8);
         P->off_keys_a = off;
         off = align_up(off + (size_t)n * kb);
         if (op == EVOSORT_OP_ARGSORT) {
@@ -365,7 +372,17 @@ evosort_status run_radix(const Plan& P, const void* keys_in, void* keys_out, con
     auto* err = reinterpret_cast<uint32_t*>(at(temp, P.off_err));
 
     EVOSORT_LAUNCH("fill_zero", s, launch_fill_zero(at(temp, P.zero_begin), P.zero_end - P.zero_begin, s));
-    EVOSORT_LAUNCH("radix_histogram", s, launch_radix_histogram(P.kd, keys_in, n, P.bits, passes, hist, s));
+    if (P.prefix0) {
+        void* counts0 = at(temp, P.off_status);  // pass 0's status words hold its tile prefixes
+        EVOSORT_LAUNCH("radix_histogram", s,
+                       launch_radix_histogram_tiles(P.kd, keys_in, n, passes, hist, counts0, (int)P.info.status_bytes,
+                                                    (uint32_t)P.info.tile_keys, (uint32_t)P.info.tiles, s));
+        EVOSORT_LAUNCH("tile_prefix", s,
+                       launch_tile_prefix(counts0, (int)P.info.status_bytes, (uint32_t)P.info.tiles,
+                                          reinterpret_cast<uint64_t*>(at(temp, P.off_blocks)), s));
+    } else {
+        EVOSORT_LAUNCH("radix_histogram", s, launch_radix_histogram(P.kd, keys_in, n, P.bits, passes, hist, s));
+    }
     EVOSORT_LAUNCH("radix_scan", s, launch_radix_scan(hist, bases, P.bits, passes, s));
 
     const bool argsort = P.op == EVOSORT_OP_ARGSORT;
@@ -421,6 +438,8 @@ evosort_status run_radix(const Plan& P, const void* keys_in, void* keys_out, con
             a.flags |= RADIX_FLAG_SKIP_KEYS;
         if (P.debug_flags & EVOSORT_DEBUG_WITHHOLD_TILE0)
             a.flags |= RADIX_FLAG_WITHHOLD_T0;
+        if (p == 0 && P.prefix0)
+            a.flags |= RADIX_FLAG_PREFIX;
         a.spin_limit = P.spin_limit;
         a.tiles = (uint32_t)P.info.tiles;
         EVOSORT_LAUNCH("radix_pass", s,

@@ -23,6 +23,19 @@ struct KeyDesc {
 hipError_t launch_radix_histogram(const KeyDesc& kd, const void* keys, int64_t n, int bits, int passes,
                                   uint64_t* hist, hipStream_t s);
 
+// The all-pass histogram of 8-bit digits (passes 4 or 8, zeroed hist) that
+// also writes, for every tile of tile_keys keys, the tile's counts of the
+// pass-0 digits: counts[tile * 256 + digit], words of status_bytes (4 or 8).
+hipError_t launch_radix_histogram_tiles(const KeyDesc& kd, const void* keys, int64_t n, int passes,
+                                        uint64_t* hist, void* counts, int status_bytes, uint32_t tile_keys,
+                                        uint32_t tiles, hipStream_t s);
+
+// Turns the per-tile counts of launch_radix_histogram_tiles, in place, into
+// each tile's exclusive prefix per digit (the sum over all earlier tiles).
+// block_sums: scratch of ceil(tiles / 64) * 256 uint64.
+hipError_t launch_tile_prefix(void* counts, int status_bytes, uint32_t tiles, uint64_t* block_sums, hipStream_t s);
+constexpr uint32_t kTilePrefixBlock = 64;  // tiles per workgroup of the prefix kernels
+
 // Exclusive prefix sums of each pass's 2^bits histogram row.
 hipError_t launch_radix_scan(const uint64_t* hist, uint64_t* bases, int bits, int passes, hipStream_t s);
 
@@ -44,6 +57,8 @@ struct RadixPassArgs {
 constexpr uint32_t RADIX_FLAG_IOTA = 1u;          // values are the input positions (argsort, first pass)
 constexpr uint32_t RADIX_FLAG_SKIP_KEYS = 2u;     // do not write keys (argsort, last pass)
 constexpr uint32_t RADIX_FLAG_WITHHOLD_T0 = 4u;   // debug: tile 0 never publishes
+constexpr uint32_t RADIX_FLAG_PREFIX = 8u;        // status holds each tile's exclusive digit prefixes, computed
+                                                  // before the pass: no publication, no look-back
 
 struct RadixShape {
     int threads;

@@ -94,6 +94,65 @@ hipError_t launch_radix_histogram(const KeyDesc& kd, const void* keys, int64_t n
     return hipSuccess;
 }
 
+hipError_t launch_radix_histogram_tiles(const KeyDesc& kd, const void* keys, int64_t n, int passes,
+                                        uint64_t* hist, void* counts, int status_bytes, uint32_t tile_keys,
+                                        uint32_t tiles, hipStream_t s)
+{
+    if (tiles == 0)
+        return hipSuccess;
+    const int copies = kHistThreads / kWave;
+    const size_t lds = ((size_t)copies * passes + 1) * 256 * 4;
+    const uint32_t grid = tiles < 4096 ? tiles : 4096;
+    auto* h = reinterpret_cast<unsigned long long*>(hist);
+#define EVOSORT_HT(KB, P, ST, U)                                                                                 \
+    do {                                                                                                       \
+        OrderMap<U> om{(U)kd.flip, (U)kd.neg};                                                                 \
+        hipLaunchKernelGGL((radix_histogram8_tiles_kernel<KB, kHistThreads, P, ST>), dim3(grid),                \
+                           dim3(kHistThreads), lds, s, reinterpret_cast<const U*>(keys), n, om, copies, h,      \
+                           reinterpret_cast<ST*>(counts), tile_keys, tiles);                                   \
+        return hipGetLastError();                                                                              \
+    } while (0)
+    if (kd.bytes == 4 && passes == 4) {
+        if (status_bytes == 4)
+            EVOSORT_HT(4, 4, uint32_t, uint32_t);
+        EVOSORT_HT(4, 4, uint64_t, uint32_t);
+    }
+    if (kd.bytes == 8 && passes == 8) {
+        if (status_bytes == 4)
+            EVOSORT_HT(8, 8, uint32_t, uint64_t);
+        EVOSORT_HT(8, 8, uint64_t, uint64_t);
+    }
+#undef EVOSORT_HT
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_tile_prefix(void* counts, int status_bytes, uint32_t tiles, uint64_t* block_sums, hipStream_t s)
+{
+    if (tiles == 0)
+        return hipSuccess;
+    const uint32_t blocks = (tiles + kTilePrefixBlock - 1) / kTilePrefixBlock;
+    if (status_bytes == 4)
+        hipLaunchKernelGGL(tile_block_sum_kernel<uint32_t>, dim3(blocks), dim3(256), 0, s,
+                           reinterpret_cast<const uint32_t*>(counts), tiles, block_sums);
+    else
+        hipLaunchKernelGGL(tile_block_sum_kernel<uint64_t>, dim3(blocks), dim3(256), 0, s,
+                           reinterpret_cast<const uint64_t*>(counts), tiles, block_sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(tile_block_scan_kernel<256>, dim3(256), dim3(256), 0, s, block_sums, blocks);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    if (status_bytes == 4)
+        hipLaunchKernelGGL(tile_prefix_kernel<uint32_t>, dim3(blocks), dim3(256), 0, s,
+                           reinterpret_cast<uint32_t*>(counts), tiles, block_sums);
+    else
+        hipLaunchKernelGGL(tile_prefix_kernel<uint64_t>, dim3(blocks), dim3(256), 0, s,
+                           reinterpret_cast<uint64_t*>(counts), tiles, block_sums);
+    return hipGetLastError();
+}
+
 hipError_t launch_radix_scan(const uint64_t* hist, uint64_t* bases, int bits, int passes, hipStream_t s)
 {
     hipLaunchKernelGGL((radix_scan_kernel<256>), dim3(passes), dim3(256), 0, s, hist, bases, 1 << bits);

@@ -165,6 +165,169 @@ __global__ __launch_bounds__(THREADS) void radix_histogram8_kernel(const typenam
     }
 }
 
+// The all-pass histogram once more, walking the keys tile by tile (the radix
+// pass's tiles of tile_keys keys): passes 1.. are counted as above, while
+// pass 0's digits are counted per tile and written to counts[tile][256].
+// With these counts pass 0 knows every tile's output offsets before it starts
+// (an exclusive scan over tiles, launch_tile_prefix) and needs no look-back:
+// the digit counts of pass 0 depend only on the input order, which is known
+// here; those of later passes depend on the previous pass's output.
+template <int KB, int THREADS, int PASSES, typename ST>
+__global__ __launch_bounds__(THREADS) void radix_histogram8_tiles_kernel(
+    const typename KeyWord<KB>::U* __restrict__ keys, int64_t n, OrderMap<typename KeyWord<KB>::U> om, int copies,
+    unsigned long long* __restrict__ hist, ST* __restrict__ counts, uint32_t tile_keys, uint32_t tiles)
+{
+    using U = typename KeyWord<KB>::U;
+    constexpr int BINS = 256;
+    constexpr int PER_COPY = PASSES * BINS;
+    extern __shared__ uint32_t lds_hist[];  // copies * PER_COPY, then the tile's pass-0 row
+    uint32_t* tile_row = lds_hist + copies * PER_COPY;
+    for (int i = threadIdx.x; i < copies * PER_COPY + BINS; i += THREADS)
+        lds_hist[i] = 0;
+    __syncthreads();
+
+    uint32_t* mine = lds_hist + (int)((threadIdx.x / kWave) % copies) * PER_COPY;
+    auto count = [&](U k) {
+        const U u = om.to_order(k);
+        const uint64_t act = ballot(true);
+        bool same = true;
+#pragma unroll
+        for (int p = PASSES - 1; p >= 0; --p) {
+            uint32_t* row = p == 0 ? tile_row : mine + p * BINS;
+            const uint32_t d = (uint32_t)(u >> (8 * p)) & 0xffu;
+            if (same) {
+                const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+                if (ballot(d == d0) == act) {
+                    if (lanes_below(act) == 0)
+                        atomicAdd(&row[d0], (uint32_t)__popcll(act));
+                    continue;
+                }
+                same = false;
+            }
+            atomicAdd(&row[d], 1u);
+        }
+    };
+
+    constexpr int VEC = 16 / KB;
+    constexpr int UNROLL = 4;
+    const bool aligned = (reinterpret_cast<uintptr_t>(keys) & 15) == 0 && (tile_keys % VEC) == 0;
+    for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int64_t start = (int64_t)t * tile_keys;
+        const int64_t len = n - start < (int64_t)tile_keys ? n - start : (int64_t)tile_keys;
+        const U* tk = keys + start;
+        int64_t done = 0;
+        if (aligned) {
+            const int64_t nvec = len / VEC;
+            const uint4* kv = reinterpret_cast<const uint4*>(tk);
+            int64_t v = threadIdx.x;
+            for (; v + (UNROLL - 1) * THREADS < nvec; v += UNROLL * THREADS) {
+                uint4 w[UNROLL];
+#pragma unroll
+                for (int u = 0; u < UNROLL; ++u)
+                    w[u] = kv[v + u * THREADS];
+#pragma unroll
+                for (int u = 0; u < UNROLL; ++u) {
+                    U k[VEC];
+                    __builtin_memcpy(k, &w[u], 16);
+#pragma unroll
+                    for (int j = 0; j < VEC; ++j)
+                        count(k[j]);
+                }
+            }
+            for (; v < nvec; v += THREADS) {
+                uint4 w = kv[v];
+                U k[VEC];
+                __builtin_memcpy(k, &w, 16);
+#pragma unroll
+                for (int j = 0; j < VEC; ++j)
+                    count(k[j]);
+            }
+            done = nvec * VEC;
+        }
+        for (int64_t i = done + threadIdx.x; i < len; i += THREADS)
+            count(tk[i]);
+        __syncthreads();
+        // the tile's pass-0 counts go out and into the pass-0 row of copy 0
+        for (int b = threadIdx.x; b < BINS; b += THREADS) {
+            const uint32_t c = tile_row[b];
+            counts[(size_t)t * BINS + b] = (ST)c;
+            lds_hist[b] += c;
+            tile_row[b] = 0;
+        }
+        __syncthreads();
+    }
+
+    for (int i = threadIdx.x; i < PER_COPY; i += THREADS) {
+        uint32_t s = 0;
+        for (int c = 0; c < copies; ++c)
+            s += lds_hist[c * PER_COPY + i];
+        if (s)
+            atomicAdd(&hist[i], (unsigned long long)s);
+    }
+}
+
+// Exclusive prefix over tiles of per-tile digit counts (256 digits, one
+// thread per digit), in three steps over blocks of kTilePrefixBlock tiles:
+// block sums, an exclusive scan of the block sums per digit, and the
+// in-place rewrite of each block's counts into prefixes.
+template <typename ST>
+__global__ __launch_bounds__(256) void tile_block_sum_kernel(const ST* __restrict__ counts, uint32_t tiles,
+                                                            uint64_t* __restrict__ block_sums)
+{
+    const uint32_t t0 = blockIdx.x * kTilePrefixBlock;
+    const uint32_t t1 = t0 + kTilePrefixBlock < tiles ? t0 + kTilePrefixBlock : tiles;
+    uint64_t s = 0;
+    for (uint32_t t = t0; t < t1; ++t)
+        s += (uint64_t)counts[(size_t)t * 256 + threadIdx.x];
+    block_sums[(size_t)blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+// One workgroup per digit: exclusive scan of block_sums[.][digit] in place.
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void tile_block_scan_kernel(uint64_t* __restrict__ block_sums, uint32_t blocks)
+{
+    static_assert(THREADS == 256, "one thread per digit");
+    __shared__ uint64_t part[256];
+    const uint32_t d = blockIdx.x;
+    const uint32_t per = (blocks + 255) / 256;
+    const uint32_t b0 = threadIdx.x * per;
+    uint64_t s = 0;
+    for (uint32_t j = 0; j < per; ++j)
+        if (b0 + j < blocks)
+            s += block_sums[(size_t)(b0 + j) * 256 + d];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint64_t y = (int)threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += y;
+        __syncthreads();
+    }
+    uint64_t run = part[threadIdx.x] - s;
+    for (uint32_t j = 0; j < per; ++j)
+        if (b0 + j < blocks) {
+            uint64_t* p = &block_sums[(size_t)(b0 + j) * 256 + d];
+            const uint64_t c = *p;
+            *p = run;
+            run += c;
+        }
+}
+
+template <typename ST>
+__global__ __launch_bounds__(256) void tile_prefix_kernel(ST* __restrict__ counts, uint32_t tiles,
+                                                         const uint64_t* __restrict__ block_sums)
+{
+    const uint32_t t0 = blockIdx.x * kTilePrefixBlock;
+    const uint32_t t1 = t0 + kTilePrefixBlock < tiles ? t0 + kTilePrefixBlock : tiles;
+    uint64_t run = block_sums[(size_t)blockIdx.x * 256 + threadIdx.x];
+    for (uint32_t t = t0; t < t1; ++t) {
+        ST* p = &counts[(size_t)t * 256 + threadIdx.x];
+        const uint64_t c = (uint64_t)*p;
+        *p = (ST)run;
+        run += c;
+    }
+}
+
 // ------------------------------------------------------------------------
 // Digit bases: exclusive scan of one histogram row per workgroup
 // ------------------------------------------------------------------------
@@ -470,7 +633,8 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
         cnt[j] = c;
         tsum += c;
     }
-    const bool publish = !((a.flags & RADIX_FLAG_WITHHOLD_T0) && tile == 0);
+    const bool prefixed = (a.flags & RADIX_FLAG_PREFIX) != 0;
+    const bool publish = !prefixed && !((a.flags & RADIX_FLAG_WITHHOLD_T0) && tile == 0);
     if (publish) {
         const ST flag = (ST)(tile == 0 ? kFlagInclusive : kFlagAggregate) << Status<ST>::kShift;
 #pragma unroll
@@ -544,7 +708,9 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
         if (b >= BINS)
             continue;
         uint64_t excl = 0;
-        if (tile > 0) {
+        if (prefixed) {
+            excl = (uint64_t)status[(size_t)tile * BINS + b];  // written before this kernel
+        } else if (tile > 0) {
             excl = look_back<ST, BINS>(status, tile, b, a.spin_limit, a.error_word);
             store_agent(&status[(size_t)tile * BINS + b],
                         (ST)(((ST)kFlagInclusive << Status<ST>::kShift) | (ST)(excl + cnt[j])));
