@@ -14,6 +14,9 @@ Prints one JSON line with the contract fields plus:
                 every launch during the timed steps, against 8 TB/s; `traffic`
                 is the HBM bytes per launch from the committed rocprofv3
                 counter summary when it was taken on the current kernel source;
+                `copy_gbs` is a plain 4 GiB device copy timed on the same GPU
+                (the practical read+write ceiling) and `frac_of_copy` the
+                pass's rate against it;
   cpu_baseline  the CPU oracle (single-threaded stable mergesort) timed on a
                 bounded sample of the same workload on the host;
   kernels       mean milliseconds per launch of every library kernel;
@@ -393,6 +396,26 @@ def run_serving_bench(es, torch, count: int, rate: float, budget_gb: float, seed
             "plain_fifo": plain}
 
 
+def copy_bandwidth(torch, nbytes: int = 4 << 30, reps: int = 10) -> float:
+    """Read + write GB/s of a plain device-to-device copy of `nbytes` (PyTorch's copy kernel), timed with
+    HIP events: the practical ceiling of a kernel that reads and writes every byte once."""
+    src = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
+
+
 def cpu_baseline(dtype_name: str, n_sample: int, seed: int):
     """The oracle, untuned, on a bounded sample of the same workload (one host thread)."""
     import numpy as np
@@ -504,6 +527,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    copy_gbs = copy_bandwidth(torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.dtype, min(args.cpu_sample, args.n), args.seed)
@@ -543,6 +568,8 @@ def main():
             "traffic": counted_traffic(args.dtype, args.n),
             "algorithmic_bytes_per_launch": algorithmic_pass_bytes(args.n, kb),
             "mean_launch_ms": round(main_res["pass_mean_ms"], 4),
+            "copy_gbs": copy_gbs,
+            "frac_of_copy": round(achieved / copy_gbs, 4) if achieved and copy_gbs else None,
         },
         "cpu_baseline": cpu,
         "kernels_ms": main_res["kernels_ms"],
