@@ -29,7 +29,9 @@ Prints one JSON line with the contract fields plus:
   serving       the request loop under Poisson arrivals (2000/s, log-uniform
                 sizes in [1e3, 1e8], int32/int64/float32, 200 GB budget):
                 p50/p99 latency and keys/s, beside a plain one-call-at-a-time
-                FIFO on the same trace (unless --no-serving).
+                FIFO on the same trace (unless --no-serving);
+  paper_sweep   the paper's nine int32 distributions at 1e8 keys, ascending
+                and descending (unless --no-paper-sweep).
 """
 from __future__ import annotations
 
@@ -416,6 +418,46 @@ def copy_bandwidth(torch, nbytes: int = 4 << 30, reps: int = 10) -> float:
     return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
 
 
+def run_paper_sweep(es, torch, n: int, seed: int, steps: int = 5):
+    """The paper's nine int32 distributions at n keys each: default parameters, ascending and descending,
+    median time of `steps` sorts after one untimed call; each output is checked ordered on the device."""
+    import numpy as np
+
+    import workloads
+
+    out = []
+    stream = torch.cuda.current_stream()
+    for dist in workloads.PAPER_DISTRIBUTIONS:
+        keys = torch.from_numpy(workloads.make(dist, np.int32, n, seed)).cuda()
+        res = torch.empty_like(keys)
+        entry = {"dist": dist}
+        for desc in (0, 1):
+            p = es.default_params(descending=desc)
+            temp = torch.empty(max(es.temp_bytes(es.OP_SORT, es.INT32, n, 0, p), 256), dtype=torch.uint8,
+                               device="cuda")
+            es.sort(keys, params=p, out=res, temp=temp)
+            times = []
+            for _ in range(steps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                es.sort(keys, params=p, out=res, temp=temp)
+                b.record(stream)
+                b.synchronize()
+                times.append(a.elapsed_time(b))
+            bad = (res[1:] > res[:-1]) if desc else (res[1:] < res[:-1])
+            if bool(bad.any().item()):
+                raise RuntimeError(f"{dist} output not ordered")
+            ms = float(np.median(times))
+            entry["descending_ms" if desc else "ms"] = round(ms, 4)
+            entry["descending_gkeys_per_s" if desc else "gkeys_per_s"] = round(n / (ms * 1e-3) / 1e9, 2)
+            del temp
+        out.append(entry)
+        del keys, res
+    torch.cuda.empty_cache()
+    return {"workload": f"the paper's nine int32 distributions at {n:.0e} keys each, default parameters",
+            "entries": out}
+
+
 def cpu_baseline(dtype_name: str, n_sample: int, seed: int):
     """The oracle, untuned, on a bounded sample of the same workload (one host thread)."""
     import numpy as np
@@ -452,6 +494,7 @@ def main():
     ap.add_argument("--batched-nseg", type=int, default=100_000)
     ap.add_argument("--no-tuned", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-paper-sweep", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-rate", type=float, default=2000.0)
     ap.add_argument("--serving-budget-gb", type=float, default=200.0)
@@ -508,6 +551,12 @@ def main():
         tuned = run_tuned_bench(es, torch, args.tuned_n, args.seed, args.tuned_pop, args.tuned_generations, 2)
         print(f"# tuned: {[(e['dist'], e['ms'], e['default_ms']) for e in tuned['entries']]}", file=sys.stderr,
               flush=True)
+
+    paper_sweep = None
+    if not args.no_paper_sweep:
+        paper_sweep = run_paper_sweep(es, torch, 100_000_000, args.seed)
+        print(f"# paper sweep: {[(e['dist'], e['ms'], e['descending_ms']) for e in paper_sweep['entries']]}",
+              file=sys.stderr, flush=True)
 
     serving = None
     if not args.no_serving:
@@ -577,6 +626,7 @@ def main():
         "batched": batched,
         "tuned": tuned,
         "serving": serving,
+        "paper_sweep": paper_sweep,
     }
     print(json.dumps(line), flush=True)
 

@@ -128,6 +128,9 @@ typedef enum evosort_path {
  *                        kernel records EVOSORT_ERR_DEVICE_TIMEOUT in temp and
  *                        finishes (the output is then undefined).
  *   debug_flags          EVOSORT_DEBUG_* bits; 0 in normal use.
+ *   descending           0: ascending order; 1: descending order, equal keys
+ *                        still in input order (the order word is complemented;
+ *                        floats: +NaN first, -0.0 after +0.0, -NaN last).
  */
 typedef struct evosort_params {
     uint32_t struct_size;
@@ -139,6 +142,8 @@ typedef struct evosort_params {
     uint32_t items_per_thread;
     uint32_t spin_limit;
     uint32_t debug_flags;
+    uint32_t descending;
+    uint32_t reserved;
 } evosort_params;
 
 /* What a call with the given arguments would do (host only; no GPU needed). */

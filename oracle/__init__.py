@@ -59,6 +59,7 @@ def _load():
     ci = ctypes.c_int
     lib.oracle_order_keys.argtypes = [ci, vp, i64, vp]
     lib.oracle_stable_perm.argtypes = [ci, vp, i64, vp]
+    lib.oracle_stable_perm_dir.argtypes = [ci, vp, i64, ci, vp]
     lib.oracle_digit_histogram.argtypes = [ci, vp, i64, ci, vp]
     lib.oracle_counting_pass.argtypes = [ci, vp, i64, ci, ci, vp]
     lib.oracle_insertion_chunks.argtypes = [ci, vp, i64, i64, vp]
@@ -106,33 +107,35 @@ def order_keys(keys: np.ndarray) -> np.ndarray:
     return out
 
 
-def stable_perm(keys: np.ndarray) -> np.ndarray:
-    """The unique stable sorting permutation (int64) of ``keys``."""
+def stable_perm(keys: np.ndarray, descending: bool = False) -> np.ndarray:
+    """The unique stable sorting permutation (int64) of ``keys``: ascending, or descending with equal keys
+    still in input order."""
     keys = _contig(keys)
     perm = np.empty(keys.size, dtype=np.int64)
-    _check(_load().oracle_stable_perm(_kind(keys), _ptr(keys), keys.size, _ptr(perm)), "stable_perm")
+    _check(_load().oracle_stable_perm_dir(_kind(keys), _ptr(keys), keys.size, 1 if descending else 0, _ptr(perm)),
+           "stable_perm")
     return perm
 
 
-def sort(keys: np.ndarray) -> np.ndarray:
+def sort(keys: np.ndarray, descending: bool = False) -> np.ndarray:
     """Result of a keys-only sort: keys gathered through the stable permutation."""
     keys = _contig(keys)
-    return keys[stable_perm(keys)]
+    return keys[stable_perm(keys, descending)]
 
 
-def sort_pairs(keys: np.ndarray, vals: np.ndarray):
+def sort_pairs(keys: np.ndarray, vals: np.ndarray, descending: bool = False):
     """Result of a key-value sort: (keys, values) gathered through the stable permutation."""
     keys = _contig(keys)
     vals = _contig(vals)
     if vals.shape[0] != keys.shape[0]:
         raise ValueError("keys and values differ in length")
-    perm = stable_perm(keys)
+    perm = stable_perm(keys, descending)
     return keys[perm], vals[perm]
 
 
-def argsort(keys: np.ndarray, index_dtype=np.int64) -> np.ndarray:
+def argsort(keys: np.ndarray, index_dtype=np.int64, descending: bool = False) -> np.ndarray:
     """Result of an argsort: the stable permutation in the requested index type."""
-    return stable_perm(keys).astype(index_dtype)
+    return stable_perm(keys, descending).astype(index_dtype)
 
 
 def _segments(offsets, n: int):
@@ -144,18 +147,18 @@ def _segments(offsets, n: int):
     return zip(offsets[:-1].tolist(), offsets[1:].tolist())
 
 
-def segmented_sort(keys: np.ndarray, offsets) -> np.ndarray:
+def segmented_sort(keys: np.ndarray, offsets, descending: bool = False) -> np.ndarray:
     """Result of a batched segmented sort: every segment keys[offsets[i]:offsets[i+1]]
     replaced by its own stable sort; keys outside the segments are unchanged."""
     keys = _contig(keys)
     out = keys.copy()
     for b, e in _segments(offsets, keys.size):
         if e - b > 1:
-            out[b:e] = sort(keys[b:e])
+            out[b:e] = sort(keys[b:e], descending)
     return out
 
 
-def segmented_sort_pairs(keys: np.ndarray, vals: np.ndarray, offsets):
+def segmented_sort_pairs(keys: np.ndarray, vals: np.ndarray, offsets, descending: bool = False):
     """Key-value version of :func:`segmented_sort` (values travel with their keys)."""
     keys = _contig(keys)
     vals = _contig(vals)
@@ -164,7 +167,7 @@ def segmented_sort_pairs(keys: np.ndarray, vals: np.ndarray, offsets):
     ko, vo = keys.copy(), vals.copy()
     for b, e in _segments(offsets, keys.size):
         if e - b > 1:
-            perm = stable_perm(keys[b:e])
+            perm = stable_perm(keys[b:e], descending)
             ko[b:e] = keys[b:e][perm]
             vo[b:e] = vals[b:e][perm]
     return ko, vo

@@ -16,6 +16,10 @@
  *           ascending, equal u ordered by index ascending,
  *   out[j]= keys[perm[j]]   (values and argsort follow from perm).
  *
+ * The descending sort is the same definition with u ordered descending (equal
+ * u still by index ascending): the stable sort a caller asking for
+ * descending order expects.
+ *
  * perm is computed by a textbook top-down stable mergesort (ties take the left
  * run), single-threaded.  Besides the whole sort, the file holds the single
  * steps the paper's two sort routines are built from, each written from the
@@ -151,18 +155,20 @@ static record_t *make_records(int kind, const void *keys, int64_t n)
 }
 
 /* Textbook top-down mergesort of r[lo, hi) using tmp as the merge buffer.
- * The merge takes from the left half unless the right element is strictly
- * smaller, so equal keys keep their order. */
-static void mergesort_records(record_t *r, record_t *tmp, int64_t lo, int64_t hi)
+ * Ascending: the merge takes from the left half unless the right element is
+ * strictly smaller; descending: unless it is strictly larger.  Either way
+ * equal keys keep their order. */
+static void mergesort_records(record_t *r, record_t *tmp, int64_t lo, int64_t hi, int descending)
 {
     if (hi - lo < 2)
         return;
     int64_t mid = lo + (hi - lo) / 2;
-    mergesort_records(r, tmp, lo, mid);
-    mergesort_records(r, tmp, mid, hi);
+    mergesort_records(r, tmp, lo, mid, descending);
+    mergesort_records(r, tmp, mid, hi, descending);
     int64_t a = lo, b = mid, k = lo;
     while (a < mid && b < hi) {
-        if (r[b].u < r[a].u)
+        const int right_first = descending ? (r[b].u > r[a].u) : (r[b].u < r[a].u);
+        if (right_first)
             tmp[k++] = r[b++];
         else
             tmp[k++] = r[a++];
@@ -174,8 +180,10 @@ static void mergesort_records(record_t *r, record_t *tmp, int64_t lo, int64_t hi
     memcpy(r + lo, tmp + lo, (size_t)(hi - lo) * sizeof(record_t));
 }
 
-/* The stable sorting permutation of keys[0, n). */
-int oracle_stable_perm(int kind, const void *keys, int64_t n, int64_t *perm_out)
+/* The stable sorting permutation of keys[0, n), ascending (descending = 0)
+ * or descending (descending = 1): indices ordered by the order key in that
+ * direction, equal keys by index ascending in both. */
+int oracle_stable_perm_dir(int kind, const void *keys, int64_t n, int descending, int64_t *perm_out)
 {
     if (!kind_bytes(kind) || n < 0 || (n > 0 && (!keys || !perm_out)))
         return -1;
@@ -188,12 +196,18 @@ int oracle_stable_perm(int kind, const void *keys, int64_t n, int64_t *perm_out)
         free(tmp);
         return -2;
     }
-    mergesort_records(r, tmp, 0, n);
+    mergesort_records(r, tmp, 0, n, descending ? 1 : 0);
     for (int64_t j = 0; j < n; ++j)
         perm_out[j] = r[j].idx;
     free(r);
     free(tmp);
     return 0;
+}
+
+/* The ascending stable sorting permutation of keys[0, n). */
+int oracle_stable_perm(int kind, const void *keys, int64_t n, int64_t *perm_out)
+{
+    return oracle_stable_perm_dir(kind, keys, n, 0, perm_out);
 }
 
 /* Number of digit positions needed to cover a key of kbytes bytes. */

@@ -74,10 +74,12 @@ class Params(ctypes.Structure):
         ("items_per_thread", ctypes.c_uint32),
         ("spin_limit", ctypes.c_uint32),
         ("debug_flags", ctypes.c_uint32),
+        ("descending", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
     def __repr__(self):
-        return "Params(" + ", ".join(f"{n}={getattr(self, n)}" for n, _ in self._fields_[1:]) + ")"
+        return "Params(" + ", ".join(f"{n}={getattr(self, n)}" for n, _ in self._fields_[1:-1]) + ")"
 
 
 class PlanInfo(ctypes.Structure):

@@ -159,6 +159,8 @@ evosort_status check_params(const evosort_params* p)
         return EVOSORT_ERR_INVALID_ARG;
     if ((p->block_threads == 0) != (p->items_per_thread == 0))
         return EVOSORT_ERR_INVALID_ARG;
+    if (p->descending > 1 || p->reserved != 0)
+        return EVOSORT_ERR_INVALID_ARG;
     return EVOSORT_OK;
 }
 
@@ -197,6 +199,7 @@ evosort_status make_plan(int op, int dtype, int64_t n, uint32_t value_bytes, con
         return EVOSORT_ERR_INVALID_ARG;
     if (!key_desc(dtype, &P->kd, &P->is_int))
         return EVOSORT_ERR_UNSUPPORTED_DTYPE;
+    P->kd.desc = p.descending ? ~0ull : 0ull;
     if (op == EVOSORT_OP_SORT) {
         if (value_bytes != 0)
             return EVOSORT_ERR_INVALID_ARG;
@@ -607,6 +610,7 @@ evosort_status make_seg_plan(int dtype, int64_t n, int64_t nseg, uint32_t value_
     bool is_int;
     if (!key_desc(dtype, &S->kd, &is_int))
         return EVOSORT_ERR_UNSUPPORTED_DTYPE;
+    S->kd.desc = p.descending ? ~0ull : 0ull;
     if (value_bytes != 0 && value_bytes != 4 && value_bytes != 8)
         return EVOSORT_ERR_UNSUPPORTED_DTYPE;
     if (n < 0 || nseg < 0 || nseg >= ((int64_t)1 << 32) - 1)

@@ -38,20 +38,27 @@ struct ValWord<8> {
 // neg = all ones, so negative values are complemented (totalOrder).
 // The keys themselves are never rewritten: the map is applied on every load
 // that needs a digit or a comparison, and original bits are what gets stored.
+// Descending order complements the order word (desc = all ones): the stable
+// sort of the complemented words is the descending stable sort.
 template <typename U>
 struct OrderMap {
     U flip;
     U neg;
+    U desc;
 
     __device__ __forceinline__ U sign_word(U k) const
     {
         using S = std::make_signed_t<U>;
         return (U)((S)k >> (sizeof(U) * 8 - 1));
     }
-    __device__ __forceinline__ U to_order(U k) const { return k ^ (flip | (sign_word(k) & neg)); }
-    // Inverse of to_order: the sign bit of an order word is set exactly for
-    // keys that were non-negative.
-    __device__ __forceinline__ U from_order(U m) const { return m ^ (flip | (~sign_word(m) & neg)); }
+    __device__ __forceinline__ U to_order(U k) const { return (k ^ (flip | (sign_word(k) & neg))) ^ desc; }
+    // Inverse of to_order: once desc is undone, the sign bit of an order word
+    // is set exactly for keys that were non-negative.
+    __device__ __forceinline__ U from_order(U m) const
+    {
+        const U a = m ^ desc;
+        return a ^ (flip | (~sign_word(a) & neg));
+    }
 };
 
 // Number of set bits of `mask` in lanes below this lane.
@@ -72,31 +79,30 @@ __device__ __forceinline__ uint32_t keep_equal_bits(uint32_t acc, uint32_t m, ui
 }
 
 // Counts one key per active lane into the digit histograms of several
-// passes: hist[p * bins + digit_p] for p = passes - 1 down to 0, where
-// digit_p(p) gives this lane's digit of pass p.  While every active lane
-// holds the same digit (skewed or presorted keys, most significant digits
-// first), one lane adds the lane count: LDS atomics of many lanes on one
-// word are executed one after another.  From the first pass whose digits
-// differ, every lane adds 1 (random keys take that path at once, after one
-// test).
+// passes: hist[p * bins + digit_p(p)] for p = passes - 1 down to 0.  LDS
+// atomics of many lanes on one word are executed one after another, so the
+// lanes holding lane 0's digit are counted by one add of their number when
+// they are many (a whole wave of presorted keys, 90 % zeros of a sparse
+// array); the other lanes add 1 each.  Random keys take the per-lane adds
+// after one compare per pass.
 template <class DigitOf>
 __device__ __forceinline__ void lds_count_passes(uint32_t* hist, int bins, int passes, DigitOf&& digit_p)
 {
     const uint64_t act = ballot(true);
-    bool same = true;
 #pragma unroll
     for (int p = passes - 1; p >= 0; --p) {
         const uint32_t d = digit_p(p);
-        if (same) {
-            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-            if (ballot(d == d0) == act) {
-                if (lanes_below(act) == 0)
-                    atomicAdd(&hist[p * bins + (int)d0], (uint32_t)__popcll(act));
-                continue;
-            }
-            same = false;
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+        const uint64_t same = ballot(d == d0);
+        const uint32_t group = (uint32_t)__popcll(same);
+        if (group >= 8) {
+            if (lanes_below(act) == 0)
+                atomicAdd(&hist[p * bins + (int)d0], group);
+            if (d != d0)
+                atomicAdd(&hist[p * bins + (int)d], 1u);
+        } else {
+            atomicAdd(&hist[p * bins + (int)d], 1u);
         }
-        atomicAdd(&hist[p * bins + (int)d], 1u);
     }
 }
 

@@ -13,6 +13,7 @@ struct KeyDesc {
     int bytes;      // 4 or 8
     uint64_t flip;  // XOR applied to every key word
     uint64_t neg;   // extra XOR for keys whose sign bit is set (floats: all ones)
+    uint64_t desc;  // all ones for descending order (the order word complemented), else 0
 };
 
 // ---------------------------------------------------------------- radix ----

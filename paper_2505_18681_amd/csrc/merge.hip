@@ -297,7 +297,7 @@ template <int KB, int VB>
 hipError_t block_sort_t(const KeyDesc& kd, const MergePlan& mp, const MergeBlockArgs& a, hipStream_t s)
 {
     using U = typename KeyWord<KB>::U;
-    OrderMap<U> om{(U)kd.flip, (U)kd.neg};
+    OrderMap<U> om{(U)kd.flip, (U)kd.neg, (U)kd.desc};
     hipLaunchKernelGGL((merge_block_sort_kernel<KB, VB>), dim3((unsigned)mp.blocks), dim3(kMergeThreads), 0, s, a,
                        om, (int)mp.t_ins, (int)mp.block_keys);
     return hipGetLastError();
@@ -308,7 +308,7 @@ hipError_t round_t(const KeyDesc& kd, const MergePlan& mp, const MergeRoundArgs&
 {
     using U = typename KeyWord<KB>::U;
     constexpr int TILE = round_tile<KB>(VB);
-    OrderMap<U> om{(U)kd.flip, (U)kd.neg};
+    OrderMap<U> om{(U)kd.flip, (U)kd.neg, (U)kd.desc};
     const RoundGeom g = round_geom(a.n, a.run, TILE);
     const int64_t grid = g.pairs * g.tpp;
     if (grid > 0x7fffffffLL)
@@ -397,10 +397,10 @@ hipError_t launch_merge_partition(const KeyDesc& kd, const MergePlan& mp, const 
     if (grid == 0)
         return hipSuccess;
     if (kd.bytes == 4) {
-        OrderMap<uint32_t> om{(uint32_t)kd.flip, (uint32_t)kd.neg};
+        OrderMap<uint32_t> om{(uint32_t)kd.flip, (uint32_t)kd.neg, (uint32_t)kd.desc};
         hipLaunchKernelGGL((merge_partition_kernel<4>), dim3((unsigned)grid), dim3(kMergeThreads), 0, s, a, om, g);
     } else {
-        OrderMap<uint64_t> om{kd.flip, kd.neg};
+        OrderMap<uint64_t> om{kd.flip, kd.neg, kd.desc};
         hipLaunchKernelGGL((merge_partition_kernel<8>), dim3((unsigned)grid), dim3(kMergeThreads), 0, s, a, om, g);
     }
     return hipGetLastError();

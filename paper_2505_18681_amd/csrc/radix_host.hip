@@ -55,13 +55,13 @@ hipError_t launch_radix_histogram(const KeyDesc& kd, const void* keys, int64_t n
         const size_t lds = (size_t)copies * passes * per_pass;
         auto* h = reinterpret_cast<unsigned long long*>(hist);
         if (kd.bytes == 4 && passes == 4) {
-            OrderMap<uint32_t> om{(uint32_t)kd.flip, (uint32_t)kd.neg};
+            OrderMap<uint32_t> om{(uint32_t)kd.flip, (uint32_t)kd.neg, (uint32_t)kd.desc};
             hipLaunchKernelGGL((radix_histogram8_kernel<4, kHistThreads, 4>), dim3(grid), dim3(kHistThreads), lds,
                                s, reinterpret_cast<const uint32_t*>(keys), n, om, copies, h);
             return hipGetLastError();
         }
         if (kd.bytes == 8 && passes == 8) {
-            OrderMap<uint64_t> om{kd.flip, kd.neg};
+            OrderMap<uint64_t> om{kd.flip, kd.neg, kd.desc};
             hipLaunchKernelGGL((radix_histogram8_kernel<8, kHistThreads, 8>), dim3(grid), dim3(kHistThreads), lds,
                                s, reinterpret_cast<const uint64_t*>(keys), n, om, copies, h);
             return hipGetLastError();
@@ -79,11 +79,11 @@ hipError_t launch_radix_histogram(const KeyDesc& kd, const void* keys, int64_t n
             copies = 1;
         const size_t lds = (size_t)copies * np * per_pass;
         if (kd.bytes == 4) {
-            OrderMap<uint32_t> om{(uint32_t)kd.flip, (uint32_t)kd.neg};
+            OrderMap<uint32_t> om{(uint32_t)kd.flip, (uint32_t)kd.neg, (uint32_t)kd.desc};
             hipLaunchKernelGGL((radix_histogram_kernel<4, kHistThreads>), dim3(grid), dim3(kHistThreads), lds, s,
                                reinterpret_cast<const uint32_t*>(keys), n, om, bits, p0, np, copies, h);
         } else {
-            OrderMap<uint64_t> om{kd.flip, kd.neg};
+            OrderMap<uint64_t> om{kd.flip, kd.neg, kd.desc};
             hipLaunchKernelGGL((radix_histogram_kernel<8, kHistThreads>), dim3(grid), dim3(kHistThreads), lds, s,
                                reinterpret_cast<const uint64_t*>(keys), n, om, bits, p0, np, copies, h);
         }
@@ -106,7 +106,7 @@ hipError_t launch_radix_histogram_tiles(const KeyDesc& kd, const void* keys, int
     auto* h = reinterpret_cast<unsigned long long*>(hist);
 #define EVOSORT_HT(KB, P, ST, U)                                                                                 \
     do {                                                                                                       \
-        OrderMap<U> om{(U)kd.flip, (U)kd.neg};                                                                 \
+        OrderMap<U> om{(U)kd.flip, (U)kd.neg, (U)kd.desc};                                                                 \
         hipLaunchKernelGGL((radix_histogram8_tiles_kernel<KB, kHistThreads, P, ST>), dim3(grid),                \
                            dim3(kHistThreads), lds, s, reinterpret_cast<const U*>(keys), n, om, copies, h,      \
                            reinterpret_cast<ST*>(counts), tile_keys, tiles);                                   \

@@ -97,9 +97,9 @@ __global__ __launch_bounds__(THREADS) void radix_histogram_kernel(const typename
 }
 
 // The same for 8-bit digits and all passes in one launch (the common case),
-// with the pass count known at compile time.  Skewed and presorted keys:
-// lds_count_passes lets one lane count a whole wave while its digits agree,
-// most significant digit first.
+// with the pass count known at compile time.  Skewed, presorted and sparse
+// keys: lds_count_passes lets one lane count the lanes that share lane 0's
+// digit when they are many.
 template <int KB, int THREADS, int PASSES>
 __global__ __launch_bounds__(THREADS) void radix_histogram8_kernel(const typename KeyWord<KB>::U* __restrict__ keys,
                                                                    int64_t n, OrderMap<typename KeyWord<KB>::U> om,
@@ -187,24 +187,25 @@ __global__ __launch_bounds__(THREADS) void radix_histogram8_tiles_kernel(
     __syncthreads();
 
     uint32_t* mine = lds_hist + (int)((threadIdx.x / kWave) % copies) * PER_COPY;
+    // as lds_count_passes, with pass 0 counted into the tile's row
     auto count = [&](U k) {
         const U u = om.to_order(k);
         const uint64_t act = ballot(true);
-        bool same = true;
 #pragma unroll
         for (int p = PASSES - 1; p >= 0; --p) {
             uint32_t* row = p == 0 ? tile_row : mine + p * BINS;
             const uint32_t d = (uint32_t)(u >> (8 * p)) & 0xffu;
-            if (same) {
-                const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-                if (ballot(d == d0) == act) {
-                    if (lanes_below(act) == 0)
-                        atomicAdd(&row[d0], (uint32_t)__popcll(act));
-                    continue;
-                }
-                same = false;
+            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+            const uint64_t same = ballot(d == d0);
+            const uint32_t group = (uint32_t)__popcll(same);
+            if (group >= 8) {
+                if (lanes_below(act) == 0)
+                    atomicAdd(&row[d0], group);
+                if (d != d0)
+                    atomicAdd(&row[d], 1u);
+            } else {
+                atomicAdd(&row[d], 1u);
             }
-            atomicAdd(&row[d], 1u);
         }
     };
 
@@ -548,8 +549,8 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
     // back: the bits are exactly the lanes of this item holding the same
     // digit (OR is order-independent, and one wave's LDS instructions run in
     // program order).  Each lane also reads the wave's running count for its
-    // digit; the lowest lane of the group then clears the bucket (a no-op when
-    // the wave took the one-digit shortcut) and adds the group size to the
+    // digit; the lowest lane of the group then clears the bucket (a no-op for
+    // lane 0's group, which never sets it) and adds the group size to the
     // count.
     // rk holds each key's rank among the wave's equal digits, 16 bits per
     // key, two keys per word (the digit is recomputed from the key later):
@@ -567,18 +568,17 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t d = (uint32_t)((om.to_order(k[i]) >> a.shift) & (U)(BINS - 1));
             const bool valid = item_valid(i);
-            uint64_t peers;
-            if (ballot(d == __builtin_amdgcn_readfirstlane(d)) == ~0ull) {
-                // one digit in the whole wave (skewed or presorted keys): the
-                // peers are the valid lanes, and no lane touches the bucket,
-                // whose atomics would otherwise be executed one lane at a time
-                peers = FULL ? ~0ull : ballot(valid);
-            } else {
-                // each lane sets its bit in the 32-bit half of the bucket that holds it
-                if (FULL || valid)
-                    atomicOr(reinterpret_cast<uint32_t*>(&bkt[d]) + (lane >> 5), 1u << (lane & 31));
-                peers = bkt[d];
-            }
+            // The lanes holding lane 0's digit know their peers from one
+            // ballot and leave the bucket alone: with skewed, presorted or
+            // sparse keys they are most of the wave, and their bucket atomics
+            // would be executed one lane at a time.  The other lanes set
+            // their bit in the 32-bit half of their digit's bucket.
+            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+            const uint64_t same = ballot(d == d0);
+            const uint64_t vmask = FULL ? ~0ull : ballot(valid);
+            if (same != ~0ull && d != d0 && (FULL || valid))
+                atomicOr(reinterpret_cast<uint32_t*>(&bkt[d]) + (lane >> 5), 1u << (lane & 31));
+            const uint64_t peers = d == d0 ? (same & vmask) : bkt[d];
             const uint32_t old = wh[d];
             const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
@@ -860,7 +860,7 @@ template <int KB, int VB, int BITS, int THREADS, int ITEMS, typename ST>
 hipError_t launch_radix_pass_t(const KeyDesc& kd, const RadixPassArgs& a, uint32_t tiles, hipStream_t s)
 {
     using U = typename KeyWord<KB>::U;
-    OrderMap<U> om{(U)kd.flip, (U)kd.neg};
+    OrderMap<U> om{(U)kd.flip, (U)kd.neg, (U)kd.desc};
     auto kernel = radix_pass_kernel<KB, VB, BITS, THREADS, ITEMS, ST>;
     static int cached = 0;  // one per instantiation
     const uint32_t resident = (uint32_t)resident_groups(kernel, THREADS, cached);
@@ -874,7 +874,7 @@ template <int KB, int VB, int BITS, int THREADS, int ITEMS>
 hipError_t launch_seg_radix_pass_t(const KeyDesc& kd, const SegPassArgs& a, uint32_t grid, hipStream_t s)
 {
     using U = typename KeyWord<KB>::U;
-    OrderMap<U> om{(U)kd.flip, (U)kd.neg};
+    OrderMap<U> om{(U)kd.flip, (U)kd.neg, (U)kd.desc};
     if (grid == 0)
         return hipSuccess;
     hipLaunchKernelGGL((seg_radix_pass_kernel<KB, VB, BITS, THREADS, ITEMS>), dim3(grid), dim3(THREADS), 0, s, a, om);

@@ -109,14 +109,13 @@ __device__ __forceinline__ void sort_segment(const SegBlockArgs& a, const OrderM
             if (wave_base + (uint32_t)(i * kWave) < len) {  // uniform across the wave
                 const uint32_t d = (uint32_t)((om.to_order(k[i]) >> shift) & (U)(BINS - 1));
                 const bool valid = off0 + (uint32_t)(i * kWave) < len;
-                uint64_t peers;
-                if (ballot(d == __builtin_amdgcn_readfirstlane(d)) == ~0ull) {
-                    peers = ballot(valid);  // one digit in the wave: no bucket atomics
-                } else {
-                    if (valid)
-                        atomicOr(reinterpret_cast<unsigned long long*>(&bkt[d]), (unsigned long long)my_bit);
-                    peers = bkt[d];
-                }
+                // lane 0's digit group from one ballot, the others through the buckets
+                const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+                const uint64_t same = ballot(d == d0);
+                const uint64_t vmask = ballot(valid);
+                if (same != ~0ull && d != d0 && valid)
+                    atomicOr(reinterpret_cast<unsigned long long*>(&bkt[d]), (unsigned long long)my_bit);
+                const uint64_t peers = d == d0 ? (same & vmask) : bkt[d];
                 const uint32_t old = wh[d];
                 const uint32_t below = lanes_below(peers);
                 if (valid && below == 0) {
@@ -247,7 +246,7 @@ hipError_t launch_class(const KeyDesc& kd, const SegBlockArgs& a, uint32_t max_g
     const uint32_t grid = max_grid < (uint32_t)resident ? max_grid : (uint32_t)resident;
     if (grid == 0)
         return hipSuccess;
-    OrderMap<U> om{(U)kd.flip, (U)kd.neg};
+    OrderMap<U> om{(U)kd.flip, (U)kd.neg, (U)kd.desc};
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(c.threads), 0, s, a, om);
     return hipGetLastError();
 }

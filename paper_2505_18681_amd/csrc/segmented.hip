@@ -287,10 +287,10 @@ hipError_t launch_seg_histogram(const KeyDesc& kd, const SegHistArgs& a, uint32_
     if (grid == 0)
         return hipSuccess;
     if (kd.bytes == 4) {
-        OrderMap<uint32_t> om{(uint32_t)kd.flip, (uint32_t)kd.neg};
+        OrderMap<uint32_t> om{(uint32_t)kd.flip, (uint32_t)kd.neg, (uint32_t)kd.desc};
         hipLaunchKernelGGL(seg_histogram_kernel<4>, dim3(grid), dim3(kSegThreads), 0, s, a, om);
     } else {
-        OrderMap<uint64_t> om{kd.flip, kd.neg};
+        OrderMap<uint64_t> om{kd.flip, kd.neg, kd.desc};
         hipLaunchKernelGGL(seg_histogram_kernel<8>, dim3(grid), dim3(kSegThreads), 0, s, a, om);
     }
     return hipGetLastError();

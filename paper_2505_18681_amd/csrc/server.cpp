@@ -445,6 +445,7 @@ evosort_status evosort_server_create(const evosort_server_config* cfg, evosort_s
     S->cfg = *cfg;
     evosort_default_params(&S->batch_params);
     S->batch_params.fallback_threshold = cfg->params.fallback_threshold;
+    S->batch_params.descending = cfg->params.descending;
     S->staging_bytes =
         align_up((size_t)cfg->batch_max_requests * sizeof(GatherItem) + ((size_t)cfg->batch_max_requests + 1) * 8);
     const size_t reserved = (size_t)cfg->streams * S->staging_bytes;

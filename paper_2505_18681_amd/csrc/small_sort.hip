@@ -162,7 +162,7 @@ template <int KB, int VB>
 hipError_t launch_t(const KeyDesc& kd, const SmallSortArgs& a, hipStream_t s)
 {
     using U = typename KeyWord<KB>::U;
-    OrderMap<U> om{(U)kd.flip, (U)kd.neg};
+    OrderMap<U> om{(U)kd.flip, (U)kd.neg, (U)kd.desc};
     hipLaunchKernelGGL((small_sort_kernel<KB, VB>), dim3(1), dim3(kSmallThreads), 0, s, a, om);
     return hipGetLastError();
 }

@@ -17,8 +17,13 @@ SRC = os.path.join(ROOT, "oracle", "evosort_oracle.c")
 
 MUTANTS = {
     "mergesort tie takes the right run": (
-        "        if (r[b].u < r[a].u)\n            tmp[k++] = r[b++];",
-        "        if (r[b].u <= r[a].u)\n            tmp[k++] = r[b++];"),
+        "descending ? (r[b].u > r[a].u) : (r[b].u < r[a].u);",
+        "descending ? (r[b].u > r[a].u) : (r[b].u <= r[a].u);"),
+    "descending mergesort tie takes the right run": (
+        "descending ? (r[b].u > r[a].u) : (r[b].u < r[a].u);",
+        "descending ? (r[b].u >= r[a].u) : (r[b].u < r[a].u);"),
+    "descending direction ignored": (
+        "mergesort_records(r, tmp, 0, n, descending ? 1 : 0);", "mergesort_records(r, tmp, 0, n, 0);"),
     "int32 offset off by one": ("(int64_t)v + 2147483648LL", "(int64_t)v + 2147483647LL"),
     "int64 offset wrong bit": ("return (uint64_t)v + (UINT64_C(1) << 63);", "return (uint64_t)v + (UINT64_C(1) << 62);"),
     "float32 negative not complemented": ("return (uint64_t)(uint32_t)~b;", "return (uint64_t)b;"),

@@ -360,3 +360,65 @@ def test_segment_sizes_recipe():
     inner = s[(s > 16) & (s < 4_000_000)]
     assert abs(np.std(np.log(inner)) - 2.0) < 0.1  # clipping trims the tails a little
     assert np.array_equal(workloads.segment_offsets([3, 0, 2]), [0, 3, 3, 5])
+
+
+# ---------------------------------------------------------------- descending --
+def _selection_desc(u):
+    """O(n^2) reference: repeatedly take the largest order key, the earliest index among equals."""
+    left = list(range(len(u)))
+    out = []
+    while left:
+        best = left[0]
+        for i in left[1:]:
+            if u[i] > u[best]:
+                best = i
+        out.append(best)
+        left.remove(best)
+    return np.array(out, dtype=np.int64)
+
+
+@pytest.mark.parametrize("dt", [np.int32, np.int64, np.uint32, np.float32, np.float64])
+def test_descending_brute_force_small(dt):
+    """Every sequence of length <= 5 over a 3-value alphabet (with ties): descending stable order."""
+    import itertools
+
+    if np.dtype(dt).kind == "f":
+        alphabet = np.array([-0.0, 0.0, 1.5], dtype=dt)
+    else:
+        alphabet = np.array([0, 7, np.iinfo(dt).max], dtype=dt)
+    for n in range(0, 6):
+        for combo in itertools.product(range(3), repeat=n):
+            keys = alphabet[list(combo)] if n else np.zeros(0, dtype=dt)
+            u = oracle.order_keys(keys)
+            assert np.array_equal(oracle.stable_perm(keys, descending=True), _selection_desc(list(u))), keys
+
+
+def test_descending_matches_numpy_lexsort_for_ints():
+    x = workloads.uniform(np.int32, 20_000, 5) % 301 - 150  # many ties, both signs
+    idx = np.arange(x.size)
+    want = np.lexsort((idx, -x.astype(np.int64)))  # primary: value descending; ties: index ascending
+    assert np.array_equal(oracle.stable_perm(x, descending=True), want)
+    y = workloads.uniform(np.int64, 20_000, 6)
+    y[::3] = y[1]
+    want = np.lexsort((np.arange(y.size), -(y.astype(np.float64))))  # distinct magnitudes apart from the ties
+    got = oracle.stable_perm(y, descending=True)
+    assert np.array_equal(y[got], y[want])
+    ties = np.flatnonzero(y[got] == y[1])
+    assert np.all(np.diff(got[ties]) > 0)  # equal keys in input order
+
+
+def test_descending_is_reversed_ascending_for_distinct_keys():
+    x = np.unique(workloads.uniform(np.float64, 5000, 7))
+    x = x[workloads.rng(8).permutation(x.size)]
+    assert np.array_equal(oracle.stable_perm(x, descending=True), oracle.stable_perm(x)[::-1])
+    pairs_k, pairs_v = oracle.sort_pairs(x, np.arange(x.size), descending=True)
+    assert np.array_equal(pairs_k.view(np.uint64), oracle.sort(x)[::-1].view(np.uint64))
+
+
+def test_descending_segments():
+    sizes = np.array([0, 1, 5, 300, 2], dtype=np.int64)
+    offs = workloads.segment_offsets(sizes)
+    keys = workloads.distinct16(np.int32, int(offs[-1]), 9)
+    got = oracle.segmented_sort(keys, offs, descending=True)
+    for b, e in zip(offs[:-1], offs[1:]):
+        assert np.array_equal(got[b:e], np.sort(keys[b:e])[::-1])

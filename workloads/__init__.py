@@ -20,6 +20,15 @@ fixed seed, 42 by default, Sec. 7.5 and the data availability statement):
 * ``float_mix``      -- N(0, 1) with a fraction replaced by values drawn from
                         {-inf, +inf, -0.0, +0.0} (no NaN).
 
+The paper's own nine int32 distributions (its experimental setup lists them,
+all mapped to [-1e9, 1e9]; ``paper_*`` names, :data:`PAPER_DISTRIBUTIONS`):
+uniform, normal (sd 1e8), exponential (scale 1e9), power law (a = 0.5), beta
+(2, 5), sparse (90 % zeros), clustered (10 centres, sd 1e8), nearly sorted (a
+linear ramp with 10 % of positions replaced at random) and duplicates (10 %
+distinct values).  They are drawn here with numpy's Generator API, so the
+values differ from the paper's legacy-seeded arrays; the shapes follow its
+recipe.
+
 Batches of arrays: :func:`segment_sizes` draws log-normal array sizes
 (round(exp(N(ln median, sigma))), clipped), :func:`segment_offsets` turns sizes
 into the nseg + 1 offsets of one buffer.
@@ -40,6 +49,55 @@ DISTRIBUTIONS = (
     "zipf",
     "all_equal",
 )
+
+PAPER_DISTRIBUTIONS = (
+    "paper_uniform",
+    "paper_normal",
+    "paper_exponential",
+    "paper_power",
+    "paper_beta",
+    "paper_sparse",
+    "paper_clustered",
+    "paper_nearly_sorted",
+    "paper_duplicates",
+)
+
+_LIM = 1_000_000_000  # the paper maps every distribution to [-1e9, 1e9]
+
+
+def paper_distribution(name: str, n: int, seed: int = DEFAULT_SEED) -> np.ndarray:
+    """One of the paper's nine int32 distributions (see the module docstring)."""
+    g = rng(seed)
+    if name == "paper_uniform":
+        return g.integers(-_LIM, _LIM, size=n, dtype=np.int64).astype(np.int32)
+    if name == "paper_normal":
+        return np.clip(g.normal(0.0, 1e8, size=n), -_LIM, _LIM).astype(np.int32)
+    if name == "paper_exponential":
+        return (np.clip(g.exponential(1e9, size=n), 0, 2 * _LIM) - _LIM).astype(np.int32)
+    if name == "paper_power":
+        return (g.power(0.5, size=n) * 2 * _LIM - _LIM).astype(np.int32)
+    if name == "paper_beta":
+        return (g.beta(2.0, 5.0, size=n) * 2 * _LIM - _LIM).astype(np.int32)
+    if name == "paper_sparse":
+        out = np.zeros(n, dtype=np.int32)
+        k = n // 10
+        pos = g.choice(n, size=k, replace=False)
+        out[pos] = g.integers(-_LIM, _LIM, size=k, dtype=np.int64).astype(np.int32)
+        return out
+    if name == "paper_clustered":
+        centres = np.linspace(-_LIM, _LIM, 10)
+        c = centres[g.integers(0, 10, size=n)]
+        return np.clip(g.normal(c, 1e8), -_LIM, _LIM).astype(np.int32)
+    if name == "paper_nearly_sorted":
+        out = np.linspace(-_LIM, _LIM, n).astype(np.int32)
+        k = n // 10
+        pos = g.choice(n, size=k, replace=False)
+        out[pos] = g.integers(-_LIM, _LIM, size=k, dtype=np.int64).astype(np.int32)
+        return out
+    if name == "paper_duplicates":
+        uniq = g.integers(-_LIM, _LIM, size=max(1, n // 10), dtype=np.int64).astype(np.int32)
+        return uniq[g.integers(0, uniq.size, size=n)]
+    raise ValueError(f"unknown distribution {name!r}")
 
 
 def rng(seed: int) -> np.random.Generator:
@@ -172,6 +230,10 @@ def float_edges(dtype) -> np.ndarray:
 
 def make(dist: str, dtype, n: int, seed: int = DEFAULT_SEED) -> np.ndarray:
     """Generator by name (see the module docstring)."""
+    if dist.startswith("paper_"):
+        if np.dtype(dtype) != np.int32:
+            raise ValueError("the paper's distributions are int32")
+        return paper_distribution(dist, n, seed)
     if dist == "uniform":
         return uniform(dtype, n, seed)
     if dist == "gaussian":
