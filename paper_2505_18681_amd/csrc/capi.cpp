@@ -668,6 +668,51 @@ evosort_status make_seg_plan(int dtype, int64_t n, int64_t nseg, uint32_t value_
     return EVOSORT_OK;
 }
 
+// A second stream per device for the short segments of a batched call, so
+// that their one-workgroup sorts (latency-bound) run beside the long
+// segments' passes (bandwidth-bound) on the caller's stream.  The caller's
+// stream forks to it after the classification and joins it at the end, with
+// events, so the call stays one capturable sequence (a graph gets two
+// branches).  Created on first use and kept; calls that fork hold `mu` from
+// the fork to the join so the events are not re-recorded in between.
+struct SideStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+struct SideStreams {
+    std::mutex mu;
+    std::map<int, SideStream> per_device;
+};
+SideStreams& side_streams()
+{
+    static SideStreams* s = new SideStreams();  // never destroyed: streams outlive static teardown order
+    return *s;
+}
+// Returns false (and no side stream) if one cannot be created; the caller
+// then runs everything on its own stream.
+bool get_side_stream(SideStream* out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    SideStreams& S = side_streams();
+    auto it = S.per_device.find(dev);
+    if (it == S.per_device.end()) {
+        SideStream ss;
+        if (hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ss.join, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        it = S.per_device.emplace(dev, ss).first;
+    }
+    *out = it->second;
+    return true;
+}
+
 evosort_status run_segmented(const SegPlan& S, const void* keys_in, void* keys_out, const void* vals_in,
                              void* vals_out, const int64_t* offsets, void* temp, hipStream_t s)
 {
@@ -726,7 +771,25 @@ evosort_status run_segmented(const SegPlan& S, const void* keys_in, void* keys_o
         EVOSORT_LAUNCH("seg_scan", s, launch_seg_scan(la, slot_grid, s));
     }
 
-    // small segments: one workgroup each, per class
+    // small segments: one workgroup each, per class; on the side stream when
+    // there are long segments too
+    bool has_small = false;
+    for (int c = 0; c < S.classes; ++c)
+        has_small = has_small || (c == 0 ? 1 : S.caps[c - 1] + 1) < S.block_limit;
+    std::unique_lock<std::mutex> side_lock(side_streams().mu, std::defer_lock);
+    SideStream side{};
+    bool forked = false;
+    if (has_small && S.nlarge_max > 0) {
+        side_lock.lock();
+        if (get_side_stream(&side)) {
+            if (hipEventRecord(side.fork, s) != hipSuccess || hipStreamWaitEvent(side.stream, side.fork, 0) != hipSuccess)
+                return hip_fail(hipGetLastError());
+            forked = true;
+        } else {
+            side_lock.unlock();
+        }
+    }
+    const hipStream_t ss = forked ? side.stream : s;
     for (int c = 0; c < S.classes; ++c) {
         // class c holds segments longer than class c-1's capacity
         const int64_t least = c == 0 ? 1 : S.caps[c - 1] + 1;
@@ -742,10 +805,12 @@ evosort_status run_segmented(const SegPlan& S, const void* keys_in, void* keys_o
         ba.list = lists + (size_t)c * S.nseg;
         ba.count = &ctr->class_count[c];
         ba.ticket = &ctr->class_ticket[c];
-        EVOSORT_LAUNCH("seg_block_sort", s,
+        EVOSORT_LAUNCH("seg_block_sort", ss,
                        launch_seg_block_sort(S.kd, S.vb, c, ba, (uint32_t)(bound < 0xffffffffLL ? bound : 0xffffffffLL),
-                                             s));
+                                             ss));
     }
+    if (forked && hipEventRecord(side.join, side.stream) != hipSuccess)
+        return hip_fail(hipGetLastError());
 
     // large segments: the passes alternate between temp and the output so
     // that the last (odd-numbered) pass writes the output
@@ -779,6 +844,8 @@ evosort_status run_segmented(const SegPlan& S, const void* keys_in, void* keys_o
                            launch_seg_radix_pass(S.kd, S.vb, S.shape, pa, (uint32_t)S.tiles_max, s));
         }
     }
+    if (forked && hipStreamWaitEvent(s, side.join, 0) != hipSuccess)  // join: the caller's stream waits
+        return hip_fail(hipGetLastError());
     return EVOSORT_OK;
 }
 
