@@ -217,7 +217,15 @@ hipError_t launch_radix_pass(const KeyDesc& kd, int val_bytes, int bits, RadixSh
     return e;
 }
 
-RadixShape seg_default_shape(int key_bytes, int val_bytes) { return radix_default_shape(key_bytes, val_bytes, kSegBits); }
+// The long segments of a batch (around 1e5 to 4e6 keys each) do better with
+// 12288-key tiles than with the single-array default for 4-byte keys
+// (measured on the 100k-array batch: 16.25 vs 16.55 ms).
+RadixShape seg_default_shape(int key_bytes, int val_bytes)
+{
+    if (key_bytes == 4)
+        return val_bytes == 4 ? RadixShape{512, 16} : RadixShape{512, 24};
+    return val_bytes == 4 ? RadixShape{512, 24} : RadixShape{512, 16};
+}
 
 bool seg_pass_available(int key_bytes, int val_bytes, RadixShape sh)
 {

@@ -185,8 +185,8 @@ def run_ga(space: GeneSpace, fitness: Callable[[tuple], float], *, seed: int = 4
 # Radix tile shapes (threads, keys per thread); (0, 0) = the library default.
 # Which of them are compiled at a given digit width is asked of evosort_plan.
 RADIX_SHAPES = ((0, 0), (256, 8), (256, 12), (256, 16), (256, 24), (256, 32), (256, 48), (512, 8), (512, 16),
-                (512, 24), (512, 32), (1024, 16))
-SEG_SHAPES = ((512, 24), (512, 16), (256, 16), (256, 8))
+                (512, 24), (512, 32), (768, 16), (768, 20), (1024, 12), (1024, 16), (1024, 20))
+SEG_SHAPES = ((512, 24), (1024, 16), (512, 16), (256, 16), (256, 8))
 
 
 def sort_space() -> GeneSpace:
@@ -452,16 +452,36 @@ def load_table(path: str) -> dict:
         return json.load(f)
 
 
+TABLE_PATH = __import__("os").path.join(__import__("os").path.dirname(__import__("os").path.abspath(__file__)),
+                                        "tuned", "mi355x.json")
+
+
+def packaged_table() -> dict:
+    """The table this package ships (written by `python -m paper_2505_18681_amd.tuner` on an MI355X), or an
+    empty table."""
+    import os
+
+    return load_table(TABLE_PATH) if os.path.exists(TABLE_PATH) else {"entries": []}
+
+
+def tuned_params(es, dtype_name: str, n: int, dist: str = "uniform"):
+    """Library params from the packaged table for a sort of n keys (see params_for)."""
+    return params_for(es, packaged_table(), dtype_name, n, dist)
+
+
 def main(argv=None):
-    """Tune the sort per distribution and size class on the current GPU and write a JSON table."""
+    """Tune the sort per key type, size class and distribution (and optionally a batch) on the current GPU and
+    write a JSON table."""
     import argparse
     import os
     import sys
 
     ap = argparse.ArgumentParser(description=main.__doc__)
-    ap.add_argument("--dtype", default="int32")
+    ap.add_argument("--dtypes", default="int32", help="comma-separated key types")
     ap.add_argument("--n", default="1e6,1e7,1e8", help="comma-separated sample sizes (size classes)")
     ap.add_argument("--dists", default="uniform", help="comma-separated distributions, or 'all'")
+    ap.add_argument("--extra", default="", help="extra dtype:n:dist entries, comma-separated")
+    ap.add_argument("--batched-nseg", type=int, default=0, help="also tune the batched sort on this many arrays")
     ap.add_argument("--pop", type=int, default=POP_SIZE)
     ap.add_argument("--generations", type=int, default=GENERATIONS)
     ap.add_argument("--reps", type=int, default=3)
@@ -478,17 +498,36 @@ def main(argv=None):
     import workloads
 
     dists = list(workloads.DISTRIBUTIONS) if args.dists == "all" else args.dists.split(",")
-    table = {"device": torch.cuda.get_device_name(0), "dtype": args.dtype,
+    jobs = [(dt, int(float(x)), dist) for dt in args.dtypes.split(",") for x in args.n.split(",") for dist in dists]
+    for item in filter(None, args.extra.split(",")):
+        dt, x, dist = item.split(":")
+        jobs.append((dt, int(float(x)), dist))
+    table = {"device": torch.cuda.get_device_name(0),
              "ga": {"pop": args.pop, "generations": args.generations, "reps": args.reps, "seed": args.seed},
              "entries": []}
-    for n in (int(float(x)) for x in args.n.split(",")):
-        for dist in dists:
-            keys = torch.from_numpy(workloads.make(dist, np.dtype(args.dtype), n, args.seed)).cuda()
-            e = tune_sort(es, keys, seed=args.seed, pop_size=args.pop, generations=args.generations, reps=args.reps)
-            e.update({"dtype": args.dtype, "dist": dist})
-            table["entries"].append(e)
-            print(json.dumps({k: e[k] for k in ("dtype", "dist", "n", "params", "ms", "default_ms")}), flush=True)
-            del keys
+    for dt, n, dist in jobs:
+        host = workloads.make(dist, np.dtype(dt), n, args.seed)
+        keys = torch.from_numpy(host.view(np.int32) if dt == "uint32" else host).cuda()
+        if dt == "uint32":
+            keys = keys.view(torch.uint32)
+        e = tune_sort(es, keys, seed=args.seed, pop_size=args.pop, generations=args.generations, reps=args.reps)
+        e.update({"dtype": dt, "dist": dist})
+        table["entries"].append(e)
+        print(json.dumps({k: e[k] for k in ("dtype", "dist", "n", "params", "ms", "default_ms", "evaluations")}),
+              flush=True)
+        del keys, host
+        torch.cuda.empty_cache()
+    if args.batched_nseg:
+        sizes = workloads.segment_sizes(args.batched_nseg, args.seed)
+        offs = workloads.segment_offsets(sizes)
+        host = workloads.uniform(np.uint32, int(offs[-1]), args.seed)
+        keys = torch.from_numpy(host.view(np.int32)).cuda().view(torch.uint32)
+        del host
+        e = tune_segmented(es, keys, torch.from_numpy(offs).cuda(), seed=args.seed, pop_size=args.pop,
+                           generations=args.generations, reps=args.reps)
+        e.update({"dtype": "uint32", "dist": "lognormal_batch"})
+        table["batched"] = e
+        print(json.dumps({k: e[k] for k in ("dtype", "n", "nseg", "params", "ms", "default_ms")}), flush=True)
     save_table(table, args.out)
 
 

@@ -122,8 +122,9 @@ def test_segmented_routes_match_the_size_classes():
     keys = _keys(np.uint32, n, 12)
     k = to_dev(keys)
     o = torch.from_numpy(offs).cuda()
-    tmp = torch.empty(es.segmented_temp_bytes(es.UINT32, n, offs.size - 1), dtype=torch.uint8, device="cuda")
-    out = es.segmented_sort(k, o, temp=tmp)
+    p = es.default_params(block_threads=512, items_per_thread=24)  # a known tile size
+    tmp = torch.empty(es.segmented_temp_bytes(es.UINT32, n, offs.size - 1, 0, p), dtype=torch.uint8, device="cuda")
+    out = es.segmented_sort(k, o, params=p, temp=tmp)
     st = es.segmented_stats(tmp)
     sizes = np.diff(offs)
     caps = [512, 2048, 8192, 16384]
