@@ -83,26 +83,31 @@ __device__ __forceinline__ uint32_t keep_equal_bits(uint32_t acc, uint32_t m, ui
 // atomics of many lanes on one word are executed one after another, so the
 // lanes holding lane 0's digit are counted by one add of their number when
 // they are many (a whole wave of presorted keys, 90 % zeros of a sparse
-// array); the other lanes add 1 each.  Random keys take the per-lane adds
-// after one compare per pass.
+// array); the other lanes add 1 each.  The test stops at the first digit
+// (most significant first) without such a group: random keys pay for one
+// test per key, skewed keys keep the shortcut on every digit that has one.
 template <class DigitOf>
 __device__ __forceinline__ void lds_count_passes(uint32_t* hist, int bins, int passes, DigitOf&& digit_p)
 {
     const uint64_t act = ballot(true);
+    bool check = true;  // wave-uniform
 #pragma unroll
     for (int p = passes - 1; p >= 0; --p) {
         const uint32_t d = digit_p(p);
-        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-        const uint64_t same = ballot(d == d0);
-        const uint32_t group = (uint32_t)__popcll(same);
-        if (group >= 8) {
-            if (lanes_below(act) == 0)
-                atomicAdd(&hist[p * bins + (int)d0], group);
-            if (d != d0)
-                atomicAdd(&hist[p * bins + (int)d], 1u);
-        } else {
-            atomicAdd(&hist[p * bins + (int)d], 1u);
+        if (check) {
+            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+            const uint64_t same = ballot(d == d0);
+            const uint32_t group = (uint32_t)__popcll(same);
+            if (group >= 8) {
+                if (lanes_below(act) == 0)
+                    atomicAdd(&hist[p * bins + (int)d0], group);
+                if (d != d0)
+                    atomicAdd(&hist[p * bins + (int)d], 1u);
+                continue;
+            }
+            check = false;
         }
+        atomicAdd(&hist[p * bins + (int)d], 1u);
     }
 }
 

@@ -191,21 +191,25 @@ __global__ __launch_bounds__(THREADS) void radix_histogram8_tiles_kernel(
     auto count = [&](U k) {
         const U u = om.to_order(k);
         const uint64_t act = ballot(true);
+        bool check = true;  // wave-uniform
 #pragma unroll
         for (int p = PASSES - 1; p >= 0; --p) {
             uint32_t* row = p == 0 ? tile_row : mine + p * BINS;
             const uint32_t d = (uint32_t)(u >> (8 * p)) & 0xffu;
-            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-            const uint64_t same = ballot(d == d0);
-            const uint32_t group = (uint32_t)__popcll(same);
-            if (group >= 8) {
-                if (lanes_below(act) == 0)
-                    atomicAdd(&row[d0], group);
-                if (d != d0)
-                    atomicAdd(&row[d], 1u);
-            } else {
-                atomicAdd(&row[d], 1u);
+            if (check) {
+                const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+                const uint64_t same = ballot(d == d0);
+                const uint32_t group = (uint32_t)__popcll(same);
+                if (group >= 8) {
+                    if (lanes_below(act) == 0)
+                        atomicAdd(&row[d0], group);
+                    if (d != d0)
+                        atomicAdd(&row[d], 1u);
+                    continue;
+                }
+                check = false;
             }
+            atomicAdd(&row[d], 1u);
         }
     };
 
