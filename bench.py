@@ -420,7 +420,8 @@ def copy_bandwidth(torch, nbytes: int = 4 << 30, reps: int = 10) -> float:
 
 def run_paper_sweep(es, torch, n: int, seed: int, steps: int = 5):
     """The paper's nine int32 distributions at n keys each: default parameters, ascending and descending,
-    median time of `steps` sorts after one untimed call; each output is checked ordered on the device."""
+    median time of `steps` sorts after a quarter second of untimed calls; each output is checked ordered
+    on the device."""
     import numpy as np
 
     import workloads
@@ -435,7 +436,10 @@ def run_paper_sweep(es, torch, n: int, seed: int, steps: int = 5):
             p = es.default_params(descending=desc)
             temp = torch.empty(max(es.temp_bytes(es.OP_SORT, es.INT32, n, 0, p), 256), dtype=torch.uint8,
                                device="cuda")
-            es.sort(keys, params=p, out=res, temp=temp)
+            t_warm = time.perf_counter()
+            while time.perf_counter() - t_warm < 0.25:  # untimed calls until the clocks are up
+                es.sort(keys, params=p, out=res, temp=temp)
+                torch.cuda.synchronize()
             times = []
             for _ in range(steps):
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -548,7 +552,7 @@ def main():
 
     tuned = None
     if not args.no_tuned:
-        tuned = run_tuned_bench(es, torch, args.tuned_n, args.seed, args.tuned_pop, args.tuned_generations, 2)
+        tuned = run_tuned_bench(es, torch, args.tuned_n, args.seed, args.tuned_pop, args.tuned_generations, 3)
         print(f"# tuned: {[(e['dist'], e['ms'], e['default_ms']) for e in tuned['entries']]}", file=sys.stderr,
               flush=True)
 

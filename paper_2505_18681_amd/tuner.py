@@ -253,6 +253,19 @@ def sort_repair(es, op: int, dtype_code: int, n: int, value_bytes: int = 0) -> C
 # --------------------------------------------------------------------------
 # GPU fitness: median wall time of the sort on resident sample data
 # --------------------------------------------------------------------------
+WARM_SECONDS = 0.25
+
+
+def _spin(call, torch, seconds: float) -> None:
+    """Runs `call` (at least 3 times) until `seconds` of wall time have passed."""
+    t0 = time.perf_counter()
+    k = 0
+    while k < 3 or time.perf_counter() - t0 < seconds:
+        call()
+        torch.cuda.synchronize()
+        k += 1
+
+
 class SortFitness:
     """f(x) = T_sort(x) (Sec. 3.2): median GPU time of one sort call, in ms.
 
@@ -302,6 +315,13 @@ class SortFitness:
         self.memo[key] = t
         return t
 
+    def warm(self, ind: tuple, seconds: float = WARM_SECONDS) -> None:
+        """Untimed sorts with one individual's params before the first timing, so that the
+        first individuals timed (the seeded defaults) do not meet an idle GPU's clocks."""
+        p = to_params(self.es, self.space.as_dict(ind))
+        tmp = self._temp(p)
+        _spin(lambda: self.es.sort(self.keys, params=p, out=self.out, temp=tmp), self.torch, seconds)
+
     def _time(self, p) -> float:
         es, torch = self.es, self.torch
         tmp = self._temp(p)
@@ -337,7 +357,7 @@ class SegmentedFitness:
         self.reference = None
         self.temp = None
 
-    def __call__(self, ind: tuple) -> float:
+    def _call(self, ind: tuple):
         es, torch = self.es, self.torch
         p = to_params(es, self.space.as_dict(ind))
         code = es.dtype_code(self.keys.dtype)
@@ -345,7 +365,15 @@ class SegmentedFitness:
         if self.temp is None or self.temp.numel() < need:
             self.temp = None
             self.temp = torch.empty(need, dtype=torch.uint8, device=self.keys.device)
-        call = lambda: es.segmented_sort(self.keys, self.offsets, params=p, out=self.out, temp=self.temp)  # noqa
+        return lambda: es.segmented_sort(self.keys, self.offsets, params=p, out=self.out, temp=self.temp)  # noqa
+
+    def warm(self, ind: tuple, seconds: float = WARM_SECONDS) -> None:
+        """Untimed batched calls with one individual's params before the first timing."""
+        _spin(self._call(ind), self.torch, seconds)
+
+    def __call__(self, ind: tuple) -> float:
+        torch = self.torch
+        call = self._call(ind)
         call()
         torch.cuda.synchronize()
         times = []
@@ -387,6 +415,7 @@ def tune_sort(es, keys, *, seed: int = 42, pop_size: int = POP_SIZE, generations
     repair = sort_repair(es, es.OP_SORT, code, keys.numel())
     base = repair(default_individual(es))
     t0 = time.perf_counter()
+    fitness.warm(base)
     res = run_ga(space, fitness, seed=seed, pop_size=pop_size, generations=generations, repair=repair,
                  seed_individuals=[base])
     # both re-timed after the search, side by side
@@ -405,6 +434,7 @@ def tune_segmented(es, keys, offsets, *, seed: int = 42, pop_size: int = POP_SIZ
     cap = es.segmented_capacity(es.dtype_code(keys.dtype))
     base = default_segmented_individual(es, cap)
     t0 = time.perf_counter()
+    fitness.warm(base)
     res = run_ga(fitness.space, fitness, seed=seed, pop_size=pop_size, generations=generations,
                  seed_individuals=[base])
     default_ms = fitness(base)
