@@ -16,6 +16,9 @@ the GPU with plain torch operations (never with this library).  Workloads:
 
 * 1e9 uniform int32 keys, default parameters (the benchmark's sort);
 * 1e8 int32 keys for each of the eight distributions of the sweep;
+* 2^30 - 1 and 2^30 int32 keys, either side of the switch from 32-bit to
+  64-bit look-back words;
+* 1e8 int32 keys of each of the paper's nine distributions, descending;
 * 1e10 uniform int32 keys (about 130 GB of HBM);
 * 2e9 float64 keys, N(0,1) with 1 % from {-inf, +inf, -0.0, +0.0}, sorted as
   pairs with an int32 payload equal to the original index.
@@ -111,6 +114,49 @@ def test_merge_routine_1e8_int32(dist):
     idx = to_np(es.argsort(d_keys, params=p))
     _check_ranks(keys, out, 3, 3)
     _check_argsort_exact(keys, out, idx)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("n", [2**30 - 1, 2**30])
+def test_lookback_word_width_boundary_int32(n):
+    """The largest sort with 32-bit look-back words (n = 2^30 - 1: counts up to 2^30 - 1 in 30 bits) and
+    the smallest with 64-bit words (n = 2^30)."""
+    es = require_gpu()
+    import torch
+
+    info = es.plan(es.OP_SORT, es.INT32, n)
+    assert info["path_name"] == "radix" and info["status_bytes"] == (4 if n < 2**30 else 8)
+    _progress(f"{n} int32: generating")
+    keys = workloads.uniform(np.int32, n, 11)
+    keys[: n // 3] = keys[n // 3: 2 * (n // 3)]  # every key of the first third appears twice: ties
+    d_keys = to_dev(keys)
+    _progress(f"{n} int32: sorting")
+    out = to_np(es.sort(d_keys))
+    idx = to_np(es.argsort(d_keys, index_dtype=torch.int32)).astype(np.int64)
+    del d_keys
+    torch.cuda.empty_cache()
+    _progress(f"{n} int32: oracle samples")
+    _check_ranks(keys, out, 4, 6)
+    _progress(f"{n} int32: exact properties")
+    _check_argsort_exact(keys, out, idx)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dist", workloads.PAPER_DISTRIBUTIONS)
+def test_paper_distributions_1e8_int32_descending(dist):
+    """The paper's nine distributions at 1e8, descending.  For int32, bitwise NOT reverses the order
+    (~k = -k - 1), so the stable descending sort of k is the stable ascending sort of ~k: oracle ranks and
+    the exact properties are taken on ~k."""
+    es = require_gpu()
+    n = 100_000_000
+    keys = workloads.make(dist, np.int32, n, 42)
+    d_keys = to_dev(keys)
+    p = es.default_params(descending=1)
+    out = to_np(es.sort(d_keys, params=p))
+    idx = to_np(es.argsort(d_keys, params=p))
+    comp = np.invert(keys)
+    _check_ranks(comp, np.invert(out), 4, 7)
+    _check_argsort_exact(comp, np.invert(out), idx)
 
 
 def _gpu_sorted_int(t):
