@@ -462,6 +462,50 @@ def run_paper_sweep(es, torch, n: int, seed: int, steps: int = 5):
             "entries": out}
 
 
+def run_vendor_compare(es, torch, n: int, seed: int, steps: int = 3):
+    """torch.sort(stable=True) on the same n uniform int32 keys, against this library's sort of (key, int64
+    index) pairs, which returns the same two arrays; both outputs are checked identical (the stable sort is
+    unique).  Median of `steps` event-timed calls after one untimed call each."""
+    import numpy as np
+
+    import workloads
+
+    keys = torch.from_numpy(workloads.uniform(np.int32, n, seed)).cuda()
+    stream = torch.cuda.current_stream()
+
+    def median_ms(fn):
+        fn()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        return float(np.median(times))
+
+    res = {}
+    torch_ms = median_ms(lambda: res.__setitem__("t", torch.sort(keys, stable=True)))
+    t_vals, t_idx = res.pop("t")
+    iota = torch.arange(n, dtype=torch.int64, device="cuda")
+    ko, vo = torch.empty_like(keys), torch.empty_like(iota)
+    p = es.default_params()
+    temp = torch.empty(max(es.temp_bytes(es.OP_SORT_PAIRS, es.INT32, n, 8, p), 256), dtype=torch.uint8,
+                       device="cuda")
+    ours_ms = median_ms(lambda: es.sort_pairs(keys, iota, params=p, keys_out=ko, values_out=vo, temp=temp))
+    identical = bool(torch.equal(t_vals, ko) and torch.equal(t_idx, vo))
+    if not identical:
+        raise RuntimeError("torch.sort and the pairs sort disagree")
+    del keys, iota, ko, vo, temp, t_vals, t_idx
+    torch.cuda.empty_cache()
+    return {"workload": f"int32 uniform full-range {n:.0e} keys, sorted keys and int64 source indices",
+            "torch_sort_ms": round(torch_ms, 3), "evosort_pairs_ms": round(ours_ms, 3),
+            "speedup": round(torch_ms / ours_ms, 2), "identical": identical,
+            "torch_version": torch.__version__}
+
+
 def cpu_baseline(dtype_name: str, n_sample: int, seed: int):
     """The oracle, untuned, on a bounded sample of the same workload (one host thread)."""
     import numpy as np
@@ -495,6 +539,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-vendor", action="store_true", help="skip the torch.sort comparison")
     ap.add_argument("--batched-nseg", type=int, default=100_000)
     ap.add_argument("--no-tuned", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -543,6 +588,12 @@ def main():
             "kernels_ms": sec["kernels_ms"],
         }
         print(f"# int64: {sec['ms_per_step']:.3f} ms/step, {sec['gkeys_per_s']:.2f} Gkeys/s", file=sys.stderr,
+              flush=True)
+
+    vendor = None
+    if not args.no_vendor and args.dtype == "int32" and args.algo == "radix":
+        vendor = run_vendor_compare(es, torch, args.n, args.seed)
+        print(f"# torch.sort {vendor['torch_sort_ms']} ms, pairs {vendor['evosort_pairs_ms']} ms", file=sys.stderr,
               flush=True)
 
     batched = None
@@ -627,6 +678,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels_ms": main_res["kernels_ms"],
         "secondary": secondary,
+        "vendor": vendor,
         "batched": batched,
         "tuned": tuned,
         "serving": serving,
