@@ -462,6 +462,79 @@ def run_paper_sweep(es, torch, n: int, seed: int, steps: int = 5):
             "entries": out}
 
 
+def run_routines_bench(es, torch, seed: int, n_merge: int = 100_000_000, steps: int = 5):
+    """The other two routines of the adaptive partition sort, on uniform int32 keys with default parameters:
+    the mergesort at n_merge keys (block sort, then merge-path rounds; roofline of each kernel from its
+    algorithmic bytes, one read and one write of every key per launch) and the one-workgroup sort at its
+    largest size (latency per call)."""
+    import numpy as np
+
+    import workloads
+
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(k):
+            fn()
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b) / k
+
+    keys = torch.from_numpy(workloads.uniform(np.int32, n_merge, seed)).cuda()
+    out = torch.empty_like(keys)
+    p = es.default_params(algo=es.ALGO_MERGE, fallback_threshold=0)
+    info = es.plan(es.OP_SORT, es.INT32, n_merge, 0, p)
+    temp = torch.empty(max(es.temp_bytes(es.OP_SORT, es.INT32, n_merge, 0, p), 256), dtype=torch.uint8,
+                       device="cuda")
+    call = lambda: es.sort(keys, params=p, out=out, temp=temp)  # noqa: E731
+    call()
+    es.profile_reset()
+    es.profile_enable(True)
+    ms = timed(call, steps)
+    es.profile_enable(False)
+    kernels = es.profile_collect()
+    es.profile_reset()
+    if not bool((out[1:] >= out[:-1]).all().item()):
+        raise RuntimeError("mergesort output is not sorted")
+    per_kernel = {k: round(v[1] / v[0], 4) for k, v in kernels.items() if v[0]}
+    launch_bytes = 2 * 4 * n_merge
+
+    def roof(name):
+        t = per_kernel.get(name)
+        if not t:
+            return None
+        gbs = launch_bytes / (t * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "mean_launch_ms": t}
+
+    merge = {"workload": f"int32 uniform full-range {n_merge:.0e} keys-only mergesort (T_ins "
+                         f"{p.insertion_threshold}, {info['merge_rounds']} merge rounds after blocks of "
+                         f"{info['merge_block_run']} keys)",
+             "ms": round(ms, 3), "gkeys_per_s": round(n_merge / (ms * 1e-3) / 1e9, 2), "kernels_ms": per_kernel,
+             "roofline": {"merge_block_sort": roof("merge_block_sort"), "merge_round": roof("merge_round")}}
+    del keys, out, temp
+    torch.cuda.empty_cache()
+
+    cap = es.plan(es.OP_SORT, es.INT32, 1)["small_capacity"]
+    n_small = cap - 1
+    keys = torch.from_numpy(workloads.uniform(np.int32, n_small, seed)).cuda()
+    out = torch.empty_like(keys)
+    p = es.default_params()
+    assert es.plan(es.OP_SORT, es.INT32, n_small, 0, p)["path_name"] == "small"
+    temp = torch.empty(max(es.temp_bytes(es.OP_SORT, es.INT32, n_small, 0, p), 256), dtype=torch.uint8,
+                       device="cuda")
+    us = 1000 * timed(lambda: es.sort(keys, params=p, out=out, temp=temp), 200)
+    if not bool((out[1:] >= out[:-1]).all().item()):
+        raise RuntimeError("small-array output is not sorted")
+    small = {"workload": f"int32 uniform {n_small} keys (one workgroup), back-to-back calls on one stream",
+             "us_per_call": round(us, 2), "mkeys_per_s": round(n_small / us, 1), "bound": "latency"}
+    return {"merge": merge, "small": small}
+
+
 def run_vendor_compare(es, torch, n: int, seed: int, steps: int = 3):
     """torch.sort(stable=True) on the same n uniform int32 keys, against this library's sort of (key, int64
     index) pairs, which returns the same two arrays; both outputs are checked identical (the stable sort is
@@ -540,6 +613,7 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-vendor", action="store_true", help="skip the torch.sort comparison")
+    ap.add_argument("--no-routines", action="store_true", help="skip the mergesort and small-array measurements")
     ap.add_argument("--batched-nseg", type=int, default=100_000)
     ap.add_argument("--no-tuned", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -595,6 +669,12 @@ def main():
         vendor = run_vendor_compare(es, torch, args.n, args.seed)
         print(f"# torch.sort {vendor['torch_sort_ms']} ms, pairs {vendor['evosort_pairs_ms']} ms", file=sys.stderr,
               flush=True)
+
+    routines = None
+    if not args.no_routines:
+        routines = run_routines_bench(es, torch, args.seed)
+        print(f"# mergesort 1e8 {routines['merge']['ms']} ms; small {routines['small']['us_per_call']} us",
+              file=sys.stderr, flush=True)
 
     batched = None
     if not args.no_batched:
@@ -679,6 +759,7 @@ def main():
         "kernels_ms": main_res["kernels_ms"],
         "secondary": secondary,
         "vendor": vendor,
+        "routines": routines,
         "batched": batched,
         "tuned": tuned,
         "serving": serving,

@@ -1,11 +1,11 @@
 // One-workgroup sort for arrays below the fallback threshold (the branch of
 // Sec. 4.3, Algorithm 6 that hands small arrays to the platform's own sort).
 //
-// The whole array sits in LDS as records (order word, input position) and is
-// sorted by a bitonic network (Batcher's construction).  Because positions are
-// unique, every record is distinct and the network's result is the stable
-// order.  Keys are written back from the order words (no second read of the
-// input), values and indices from the recorded positions.
+// One launch of one workgroup: the one-workgroup LSD radix sort (8-bit
+// digits; keys, values or indices stay in registers and LDS for every pass),
+// with the workgroup shape picked by the array length so that short arrays do
+// not pay for the ranks of empty items.  Stable, like every routine here.
+#include "block_lsd.hpp"
 #include "common.hpp"
 #include "small_sort.hpp"
 
@@ -13,158 +13,57 @@ namespace evosort {
 
 namespace {
 
-constexpr int kSmallThreads = 1024;
-
-// 4-byte keys: one 64-bit word per record, order word above the position, so
-// one integer comparison orders (key, position) pairs.
-struct Rec4 {
-    using Word = uint64_t;
-    static constexpr Word kPad = ~0ull;
+// Workgroup shapes, smallest first; the last one holds the capacity.  Wave w
+// holds keys [w*64*items, (w+1)*64*items), so a shape with few items per
+// thread keeps every wave of the workgroup busy on a short array.
+struct SmallShape {
+    int threads;
+    int items;
 };
+constexpr int kSmallShapeCount = 6;
+constexpr SmallShape kSmallShapes4[kSmallShapeCount] = {{64, 8}, {256, 4}, {256, 8}, {512, 8}, {1024, 8}, {1024, 16}};
+constexpr SmallShape kSmallShapes8[kSmallShapeCount] = {{64, 8}, {256, 4}, {256, 8}, {512, 8}, {1024, 8}, {512, 16}};
+static_assert(1024 * 16 == kSmallCapacity4 && 512 * 16 == kSmallCapacity8, "the largest shape holds the capacity");
 
-template <int KB>
-struct SmallLds;
-template <>
-struct SmallLds<4> {
-    uint64_t rec[kSmallCapacity4];
-};
-// 8-byte keys: order words and positions in two arrays, compared as pairs.
-template <>
-struct SmallLds<8> {
-    uint64_t key[kSmallCapacity8];
-    uint32_t pos[kSmallCapacity8];
-};
-
-template <int KB, int VB>
-__global__ __launch_bounds__(kSmallThreads) void small_sort_kernel(SmallSortArgs a,
-                                                                   OrderMap<typename KeyWord<KB>::U> om)
+// Keys and values share the staging area unless that would not fit in LDS.
+template <int KB, int VB, int THREADS, int ITEMS>
+constexpr bool split_staging()
 {
-    using U = typename KeyWord<KB>::U;
-    __shared__ SmallLds<KB> L;
-    const int n = (int)a.n;
-    int m = 1;
-    while (m < n)
-        m <<= 1;
-    const U* keys_in = reinterpret_cast<const U*>(a.keys_in);
-
-    // load and pad to a power of two
-    for (int i = threadIdx.x; i < m; i += kSmallThreads) {
-        if constexpr (KB == 4) {
-            L.rec[i] = i < n ? ((uint64_t)om.to_order(keys_in[i]) << 32) | (uint32_t)i : Rec4::kPad;
-        } else {
-            L.key[i] = i < n ? om.to_order(keys_in[i]) : ~0ull;
-            L.pos[i] = i < n ? (uint32_t)i : 0xffffffffu;
-        }
-    }
-    __syncthreads();
-
-    // bitonic network: stage k builds sorted runs of length k
-    for (int k = 2; k <= m; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < (m >> 1); t += kSmallThreads) {
-                const int lo = 2 * j * (t / j) + (t % j);
-                const int hi = lo + j;
-                const bool up = (lo & k) == 0;
-                if constexpr (KB == 4) {
-                    const uint64_t x = L.rec[lo], y = L.rec[hi];
-                    if ((x > y) == up) {
-                        L.rec[lo] = y;
-                        L.rec[hi] = x;
-                    }
-                } else {
-                    const uint64_t xk = L.key[lo], yk = L.key[hi];
-                    const uint32_t xp = L.pos[lo], yp = L.pos[hi];
-                    const bool gt = xk > yk || (xk == yk && xp > yp);
-                    if (gt == up) {
-                        L.key[lo] = yk;
-                        L.key[hi] = xk;
-                        L.pos[lo] = yp;
-                        L.pos[hi] = xp;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-
-    // Each thread owns positions threadIdx.x + r * kSmallThreads.
-    constexpr int R = (KB == 4 ? kSmallCapacity4 : kSmallCapacity8) / kSmallThreads;
-    U kout[R];
-    uint32_t src[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = threadIdx.x + r * kSmallThreads;
-        if (i < n) {
-            if constexpr (KB == 4) {
-                kout[r] = om.from_order((U)(L.rec[i] >> 32));
-                src[r] = (uint32_t)L.rec[i];
-            } else {
-                kout[r] = om.from_order(L.key[i]);
-                src[r] = L.pos[i];
-            }
-        }
-    }
-
-    if constexpr (VB != 0) {
-        using V = typename ValWord<VB>::T;
-        if (a.mode == SMALL_MODE_PAIRS) {
-            // Values may be sorted in place: every value is read and parked in
-            // LDS (over the records, after a barrier) before any is written.
-            const V* vals_in = reinterpret_cast<const V*>(a.vals_in);
-            V vin[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int i = threadIdx.x + r * kSmallThreads;
-                if (i < n)
-                    vin[r] = vals_in[src[r]];
-            }
-            __syncthreads();
-            V* park = reinterpret_cast<V*>(&L);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int i = threadIdx.x + r * kSmallThreads;
-                if (i < n)
-                    park[i] = vin[r];
-            }
-            __syncthreads();
-            V* vals_out = reinterpret_cast<V*>(a.vals_out);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int i = threadIdx.x + r * kSmallThreads;
-                if (i < n)
-                    vals_out[i] = park[i];
-            }
-        } else {
-            V* idx_out = reinterpret_cast<V*>(a.vals_out);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int i = threadIdx.x + r * kSmallThreads;
-                if (i < n)
-                    idx_out[i] = (V)src[r];
-            }
-        }
-    }
-    if (a.mode != SMALL_MODE_ARGSORT) {
-        U* keys_out = reinterpret_cast<U*>(a.keys_out);
-        // keys come from LDS, so writing over keys_in (in place) is safe once
-        // every thread has loaded: the barriers above order that.
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int i = threadIdx.x + r * kSmallThreads;
-            if (i < n)
-                keys_out[i] = kout[r];
-        }
-    }
+    return (size_t)THREADS * ITEMS * (KB + VB) > 128 * 1024;
 }
 
-template <int KB, int VB>
-hipError_t launch_t(const KeyDesc& kd, const SmallSortArgs& a, hipStream_t s)
+template <int KB, int VB, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void small_sort_kernel(SmallSortArgs a, OrderMap<typename KeyWord<KB>::U> om)
+{
+    constexpr bool SPLIT = split_staging<KB, VB, THREADS, ITEMS>();
+    __shared__ BlockLsdLds<KB, VB, THREADS, ITEMS, SPLIT> L;
+    const bool argsort = a.mode == SMALL_MODE_ARGSORT;
+    const BlockLsdIo io{a.keys_in, a.keys_out, a.vals_in, a.vals_out, argsort, argsort};
+    block_lsd_sort<KB, VB, THREADS, ITEMS, SPLIT>(io, om, L, 0, (uint32_t)a.n);
+}
+
+template <int KB, int VB, int THREADS, int ITEMS>
+hipError_t launch_shape(const KeyDesc& kd, const SmallSortArgs& a, hipStream_t s)
 {
     using U = typename KeyWord<KB>::U;
+    static_assert(sizeof(BlockLsdLds<KB, VB, THREADS, ITEMS, split_staging<KB, VB, THREADS, ITEMS>()>) <=
+                      160 * 1024,
+                  "one workgroup fits in one CU's LDS");
     OrderMap<U> om{(U)kd.flip, (U)kd.neg, (U)kd.desc};
-    hipLaunchKernelGGL((small_sort_kernel<KB, VB>), dim3(1), dim3(kSmallThreads), 0, s, a, om);
+    hipLaunchKernelGGL((small_sort_kernel<KB, VB, THREADS, ITEMS>), dim3(1), dim3(THREADS), 0, s, a, om);
     return hipGetLastError();
+}
+
+// The first shape, from index I on, that holds n keys.
+template <int KB, int VB, int I>
+hipError_t launch_t(const KeyDesc& kd, const SmallSortArgs& a, hipStream_t s)
+{
+    constexpr SmallShape sh = KB == 4 ? kSmallShapes4[I] : kSmallShapes8[I];
+    if constexpr (I + 1 < kSmallShapeCount) {
+        if (a.n > (int64_t)sh.threads * sh.items)
+            return launch_t<KB, VB, I + 1>(kd, a, s);
+    }
+    return launch_shape<KB, VB, sh.threads, sh.items>(kd, a, s);
 }
 
 }  // namespace
@@ -177,20 +76,22 @@ int64_t small_sort_capacity(int key_bytes, int val_bytes)
 
 hipError_t launch_small_sort(const KeyDesc& kd, int val_bytes, const SmallSortArgs& a, hipStream_t s)
 {
-    if (a.n > small_sort_capacity(kd.bytes, val_bytes))
+    if (a.n < 0 || a.n > small_sort_capacity(kd.bytes, val_bytes))
         return hipErrorInvalidValue;
+    if (a.n == 0)
+        return hipSuccess;
     if (kd.bytes == 4) {
         if (val_bytes == 0)
-            return launch_t<4, 0>(kd, a, s);
+            return launch_t<4, 0, 0>(kd, a, s);
         if (val_bytes == 4)
-            return launch_t<4, 4>(kd, a, s);
-        return launch_t<4, 8>(kd, a, s);
+            return launch_t<4, 4, 0>(kd, a, s);
+        return launch_t<4, 8, 0>(kd, a, s);
     }
     if (val_bytes == 0)
-        return launch_t<8, 0>(kd, a, s);
+        return launch_t<8, 0, 0>(kd, a, s);
     if (val_bytes == 4)
-        return launch_t<8, 4>(kd, a, s);
-    return launch_t<8, 8>(kd, a, s);
+        return launch_t<8, 4, 0>(kd, a, s);
+    return launch_t<8, 8, 0>(kd, a, s);
 }
 
 }  // namespace evosort

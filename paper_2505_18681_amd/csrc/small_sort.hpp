@@ -8,8 +8,8 @@
 
 namespace evosort {
 
-// Largest n the one-workgroup sort takes: the records of the whole array must
-// fit in LDS (8 bytes per 4-byte key: 128 KB; 12 bytes per 8-byte key: 96 KB).
+// Largest n the one-workgroup sort takes: the whole array (keys and values,
+// or indices) stays in one workgroup's registers and LDS for every pass.
 constexpr int kSmallCapacity4 = 16384;
 constexpr int kSmallCapacity8 = 8192;
 

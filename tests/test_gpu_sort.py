@@ -42,7 +42,8 @@ def test_sort_all_ops(path, dt, n):
 
 
 @pytest.mark.parametrize("dt", DTYPES)
-@pytest.mark.parametrize("n", [2, 3, 100, 1000, 4095, 8191, 8192])
+# sizes on both sides of every workgroup shape of the one-workgroup sort
+@pytest.mark.parametrize("n", [2, 3, 100, 512, 513, 1000, 1025, 2048, 2049, 4095, 4097, 8191, 8192, 8193, 16383])
 def test_small_path(dt, n):
     es = require_gpu()
     cap = es.plan(es.OP_SORT, es.dtype_code(_torch_dtype(dt)), n)["small_capacity"]
