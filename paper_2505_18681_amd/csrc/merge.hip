@@ -14,9 +14,16 @@
 //                            runs (merge path) finds how many outputs come from
 //                            the left run; ties go to the left run;
 //   merge_round_kernel       one workgroup per output tile loads its two input
-//                            slices into LDS, places every element by a binary
-//                            search in the other slice, and writes the tile out
-//                            coalesced.
+//                            slices into LDS, merges them, and writes the tile
+//                            out coalesced.
+//
+// Every merge inside LDS (the block's levels and a round's tile) is split the
+// same way: each thread owns a run of consecutive outputs, finds where its run
+// starts on both inputs by one merge-path search, then merges its run
+// sequentially with the two heads in registers: one LDS read and one write
+// per element instead of a binary search per element.  LDS arrays are padded
+// by one element every 16, so that the threads' runs start in different
+// banks.
 //
 // Stability: inside a block, records carry their position, so all records
 // are distinct and every merge is exact.  Across blocks, the merge takes the
@@ -28,7 +35,13 @@ namespace evosort {
 
 namespace {
 
-constexpr int kMergeThreads = 256;
+constexpr int kPartitionThreads = 256;  // partition kernel
+constexpr int kRoundThreads = 512;      // round kernel
+constexpr int kBlockSortThreads = 512;  // block sort
+
+// LDS index of element p of a padded array: one spare element every 16.
+__device__ __forceinline__ int pad16(int p) { return p + (p >> 4); }
+constexpr int padded16(int n) { return n + (n >> 4) + 1; }
 
 // ---------------------------------------------------------------- records --
 template <int KB>
@@ -40,6 +53,8 @@ struct Rec<4> {
     static __device__ __forceinline__ uint32_t ord(W r) { return (uint32_t)(r >> 32); }
     static __device__ __forceinline__ uint32_t pos(W r) { return (uint32_t)r; }
     static __device__ __forceinline__ bool less(W a, W b) { return a < b; }
+    // above every record (positions are below 2^32 - 1)
+    static __device__ __forceinline__ W top() { return ~0ull; }
 };
 template <>
 struct Rec<8> {
@@ -55,40 +70,93 @@ struct Rec<8> {
     {
         return a.ord < b.ord || (a.ord == b.ord && a.pos < b.pos);
     }
+    static __device__ __forceinline__ W top() { return W{~0ull, 0xffffffffu, 0u}; }
 };
 
+// Records of the block sort.  Keys-only blocks hold bare order words: a
+// chunk ranks a key against its chunk mates by (word, position), positions
+// being the records' indices, and the merges take the left run's record on
+// equal words, so the block is stable without storing positions.  With values
+// (or indices) a record also carries the key's position in the block, which
+// tells where its value is parked.
+template <int KB, int VB>
+struct BlockRec {
+    using R = Rec<KB>;
+    using W = typename R::W;
+    static constexpr bool kBare = false;
+    static __device__ __forceinline__ W make(typename KeyWord<KB>::U ord, uint32_t pos) { return R::make(ord, pos); }
+    static __device__ __forceinline__ typename KeyWord<KB>::U ord(const W& r) { return (typename KeyWord<KB>::U)R::ord(r); }
+    static __device__ __forceinline__ uint32_t pos(const W& r) { return R::pos(r); }
+    static __device__ __forceinline__ bool less(const W& a, const W& b) { return R::less(a, b); }
+    // x (at index jx) comes before y (at index iy) in the stable order
+    static __device__ __forceinline__ bool before(const W& x, int, const W& y, int) { return R::less(x, y); }
+    static __device__ __forceinline__ W top() { return R::top(); }
+};
 template <int KB>
+struct BlockRec<KB, 0> {
+    using W = typename KeyWord<KB>::U;
+    static constexpr bool kBare = true;
+    static __device__ __forceinline__ W make(W ord, uint32_t) { return ord; }
+    static __device__ __forceinline__ W ord(W r) { return r; }
+    static __device__ __forceinline__ bool less(W a, W b) { return a < b; }
+    static __device__ __forceinline__ bool before(W x, int jx, W y, int iy) { return x < y || (x == y && jx < iy); }
+    static __device__ __forceinline__ W top() { return ~(W)0; }
+};
+
+// Keys per block-sort workgroup: 4096, or 2048 for 16-byte records.
+template <int KB, int VB>
 constexpr int block_cap()
 {
-    return KB == 4 ? 4096 : 2048;
+    return KB == 8 && VB != 0 ? 2048 : 4096;
 }
 
-// Number of records in buf[lo, hi) that are less than r.
-template <int KB>
-__device__ __forceinline__ int count_less(const typename Rec<KB>::W* buf, int lo, int hi, const typename Rec<KB>::W& r)
+// Merges the sorted runs A = src[a0, a0 + na) and B = src[b0, b0 + nb)
+// (padded indices) and writes outputs [k, k_end) of the merge to
+// dst[d0 + k, d0 + k_end).  `less` is the merge order with ties already
+// decided: an A element goes first iff !less(B element, A element).  Returns
+// nothing; every thread calls it for its own output run.
+template <typename T, typename Less, typename Emit>
+__device__ __forceinline__ void merge_run(const T* src, int a0, int na, int b0, int nb, int k, int k_end,
+                                          const T& top, Less less, Emit emit)
 {
-    int a = lo, b = hi;
-    while (a < b) {
-        const int mid = (a + b) >> 1;
-        if (Rec<KB>::less(buf[mid], r))
-            a = mid + 1;
+    // merge path: i = A elements among the first k outputs
+    int lo = k - nb > 0 ? k - nb : 0;
+    int hi = k < na ? k : na;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (!less(src[pad16(b0 + k - 1 - mid)], src[pad16(a0 + mid)]))
+            lo = mid + 1;  // A[mid] goes before B[k-1-mid]
         else
-            b = mid;
+            hi = mid;
     }
-    return a - lo;
+    int i = lo, j = k - lo;
+    T ha = i < na ? src[pad16(a0 + i)] : top;
+    T hb = j < nb ? src[pad16(b0 + j)] : top;
+    for (int o = k; o < k_end; ++o) {
+        const bool take_a = j >= nb || (i < na && !less(hb, ha));
+        if (take_a) {
+            emit(o, ha, a0 + i);
+            ++i;
+            ha = i < na ? src[pad16(a0 + i)] : top;
+        } else {
+            emit(o, hb, b0 + j);
+            ++j;
+            hb = j < nb ? src[pad16(b0 + j)] : top;
+        }
+    }
 }
 
 template <int KB, int VB>
-__global__ __launch_bounds__(kMergeThreads) void merge_block_sort_kernel(MergeBlockArgs a,
-                                                                         OrderMap<typename KeyWord<KB>::U> om,
-                                                                         int t_ins, int block_keys)
+__global__ __launch_bounds__(kBlockSortThreads) void merge_block_sort_kernel(MergeBlockArgs a,
+                                                                             OrderMap<typename KeyWord<KB>::U> om,
+                                                                             int t_ins, int block_keys)
 {
     using U = typename KeyWord<KB>::U;
     using V = typename ValWord<VB>::T;
-    using R = Rec<KB>;
+    using R = BlockRec<KB, VB>;
     using W = typename R::W;
-    constexpr int CAP = block_cap<KB>();
-    __shared__ W buf[2][CAP];
+    constexpr int CAP = block_cap<KB, VB>();
+    __shared__ W buf[2][padded16(CAP)];
     __shared__ V vpark[VB ? CAP : 1];
 
     const int64_t start = (int64_t)blockIdx.x * block_keys;
@@ -98,8 +166,8 @@ __global__ __launch_bounds__(kMergeThreads) void merge_block_sort_kernel(MergeBl
 
     // Load the block.  Values are parked in LDS now, so that writing them
     // back over vals_in (in place) cannot race with reading them.
-    for (int i = threadIdx.x; i < nb; i += kMergeThreads) {
-        buf[0][i] = R::make(om.to_order(keys_in[start + i]), (uint32_t)i);
+    for (int i = threadIdx.x; i < nb; i += kBlockSortThreads) {
+        buf[0][pad16(i)] = R::make(om.to_order(keys_in[start + i]), (uint32_t)i);
         if constexpr (VB != 0) {
             const V* vals_in = reinterpret_cast<const V*>(a.vals_in);
             vpark[i] = a.iota ? (V)(start + i) : vals_in[start + i];
@@ -109,42 +177,46 @@ __global__ __launch_bounds__(kMergeThreads) void merge_block_sort_kernel(MergeBl
 
     // Chunks of t_ins: place each record at (chunk start + number of smaller
     // records in its chunk).
-    for (int i = threadIdx.x; i < nb; i += kMergeThreads) {
+    for (int i = threadIdx.x; i < nb; i += kBlockSortThreads) {
         const int c0 = (i / t_ins) * t_ins;
         const int c1 = c0 + t_ins < nb ? c0 + t_ins : nb;
-        const W r = buf[0][i];
+        const W r = buf[0][pad16(i)];
         int rank = 0;
         for (int j = c0; j < c1; ++j)
-            rank += R::less(buf[0][j], r) ? 1 : 0;
-        buf[1][c0 + rank] = r;
+            rank += R::before(buf[0][pad16(j)], j, r, i) ? 1 : 0;
+        buf[1][pad16(c0 + rank)] = r;
     }
     __syncthreads();
 
-    // Pairwise merges inside the block, run length doubling from t_ins.
+    // Pairwise merges inside the block, run length doubling from t_ins; on
+    // equal records the left run's goes first.
+    const int per = (nb + kBlockSortThreads - 1) / kBlockSortThreads;
     int cur = 1;
     for (int L = t_ins; L < nb; L *= 2) {
-        for (int i = threadIdx.x; i < nb; i += kMergeThreads) {
-            const int s = (i / (2 * L)) * (2 * L);
+        const W* src = buf[cur];
+        W* dst = buf[cur ^ 1];
+        int o = threadIdx.x * per;
+        const int o_end = o + per < nb ? o + per : nb;
+        while (o < o_end) {  // the thread's outputs may span pairs of runs
+            const int s = (o / (2 * L)) * (2 * L);
             const int mid = s + L < nb ? s + L : nb;
             const int e = s + 2 * L < nb ? s + 2 * L : nb;
-            const W r = buf[cur][i];
-            int p;
-            if (i < mid)
-                p = (i - s) + count_less<KB>(buf[cur], mid, e, r);
-            else
-                p = (i - mid) + count_less<KB>(buf[cur], s, mid, r);
-            buf[cur ^ 1][s + p] = r;
+            const int stop = o_end < e ? o_end : e;
+            merge_run<W>(src, s, mid - s, mid, e - mid, o - s, stop - s, R::top(),
+                         [](const W& x, const W& y) { return R::less(x, y); },
+                         [&](int q, const W& r, int) { dst[pad16(s + q)] = r; });
+            o = stop;
         }
         __syncthreads();
         cur ^= 1;
     }
 
     U* keys_out = reinterpret_cast<U*>(a.keys_out);
-    for (int i = threadIdx.x; i < nb; i += kMergeThreads) {
-        const W r = buf[cur][i];
+    for (int i = threadIdx.x; i < nb; i += kBlockSortThreads) {
+        const W r = buf[cur][pad16(i)];
         if (!a.skip_keys)
             keys_out[start + i] = om.from_order((U)R::ord(r));
-        if constexpr (VB != 0) {
+        if constexpr (!R::kBare) {
             V* vals_out = reinterpret_cast<V*>(a.vals_out);
             vals_out[start + i] = vpark[R::pos(r)];
         }
@@ -170,12 +242,12 @@ __host__ __device__ inline RoundGeom round_geom(int64_t n, int64_t run, int tile
 }
 
 template <int KB>
-__global__ __launch_bounds__(kMergeThreads) void merge_partition_kernel(MergeRoundArgs a,
+__global__ __launch_bounds__(kPartitionThreads) void merge_partition_kernel(MergeRoundArgs a,
                                                                         OrderMap<typename KeyWord<KB>::U> om,
                                                                         RoundGeom g)
 {
     using U = typename KeyWord<KB>::U;
-    const int64_t idx = (int64_t)blockIdx.x * kMergeThreads + threadIdx.x;
+    const int64_t idx = (int64_t)blockIdx.x * kPartitionThreads + threadIdx.x;
     const int64_t total = g.pairs * (g.tpp + 1);
     if (idx >= total)
         return;
@@ -203,16 +275,17 @@ __global__ __launch_bounds__(kMergeThreads) void merge_partition_kernel(MergeRou
 }
 
 template <int KB, int VB, int TILE>
-__global__ __launch_bounds__(kMergeThreads) void merge_round_kernel(MergeRoundArgs a,
+__global__ __launch_bounds__(kRoundThreads) void merge_round_kernel(MergeRoundArgs a,
                                                                     OrderMap<typename KeyWord<KB>::U> om,
                                                                     RoundGeom g)
 {
     using U = typename KeyWord<KB>::U;
     using V = typename ValWord<VB>::T;
-    __shared__ U s_in[TILE];
-    __shared__ U s_out[TILE];
+    constexpr int PER = TILE / kRoundThreads;
+    __shared__ U s_in[padded16(TILE)];
+    __shared__ U s_out[padded16(TILE)];
     __shared__ V v_in[VB ? TILE : 1];
-    __shared__ V v_out[VB ? TILE : 1];
+    __shared__ V v_out[VB ? padded16(TILE) : 1];
 
     const int64_t pair = (int64_t)blockIdx.x / g.tpp;
     const int64_t t = (int64_t)blockIdx.x % g.tpp;
@@ -236,54 +309,37 @@ __global__ __launch_bounds__(kMergeThreads) void merge_round_kernel(MergeRoundAr
     const int ca = (int)(a1 - a0), cb = (int)(b1 - b0);
     const int cnt = ca + cb;
 
+    // the tile's A slice, then its B slice
     const U* keys_in = reinterpret_cast<const U*>(a.keys_in);
     const V* vals_in = reinterpret_cast<const V*>(a.vals_in);
-    for (int i = threadIdx.x; i < cnt; i += kMergeThreads) {
+    for (int i = threadIdx.x; i < cnt; i += kRoundThreads) {
         const int64_t src = i < ca ? s + a0 + i : s + na + b0 + (i - ca);
-        s_in[i] = om.to_order(keys_in[src]);
+        s_in[pad16(i)] = om.to_order(keys_in[src]);
         if constexpr (VB != 0)
             v_in[i] = vals_in[src];
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < cnt; i += kMergeThreads) {
-        const U x = s_in[i];
-        int p;
-        if (i < ca) {
-            // A element: after every B element strictly smaller
-            int lo = ca, hi = cnt;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (s_in[mid] < x)
-                    lo = mid + 1;
-                else
-                    hi = mid;
-            }
-            p = i + (lo - ca);
-        } else {
-            // B element: after every A element smaller or equal
-            int lo = 0, hi = ca;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (s_in[mid] <= x)
-                    lo = mid + 1;
-                else
-                    hi = mid;
-            }
-            p = (i - ca) + lo;
-        }
-        s_out[p] = x;
-        if constexpr (VB != 0)
-            v_out[p] = v_in[i];
+    {
+        const int o = threadIdx.x * PER;
+        const int o_end = o + PER < cnt ? o + PER : cnt;
+        if (o < o_end)
+            // ties favour the A run: an A element goes first unless B's is smaller
+            merge_run<U>(s_in, 0, ca, ca, cb, o, o_end, (U)~(U)0, [](U x, U y) { return x < y; },
+                         [&](int q, U key, int from) {
+                             s_out[pad16(q)] = key;
+                             if constexpr (VB != 0)
+                                 v_out[pad16(q)] = v_in[from];
+                         });
     }
     __syncthreads();
     U* keys_out = reinterpret_cast<U*>(a.keys_out);
     V* vals_out = reinterpret_cast<V*>(a.vals_out);
-    for (int i = threadIdx.x; i < cnt; i += kMergeThreads) {
+    for (int i = threadIdx.x; i < cnt; i += kRoundThreads) {
         const int64_t dst = s + k0 + i;
         if (!a.skip_keys)
-            keys_out[dst] = om.from_order(s_out[i]);
+            keys_out[dst] = om.from_order(s_out[pad16(i)]);
         if constexpr (VB != 0)
-            vals_out[dst] = v_out[i];
+            vals_out[dst] = v_out[pad16(i)];
     }
 }
 
@@ -298,7 +354,7 @@ hipError_t block_sort_t(const KeyDesc& kd, const MergePlan& mp, const MergeBlock
 {
     using U = typename KeyWord<KB>::U;
     OrderMap<U> om{(U)kd.flip, (U)kd.neg, (U)kd.desc};
-    hipLaunchKernelGGL((merge_block_sort_kernel<KB, VB>), dim3((unsigned)mp.blocks), dim3(kMergeThreads), 0, s, a,
+    hipLaunchKernelGGL((merge_block_sort_kernel<KB, VB>), dim3((unsigned)mp.blocks), dim3(kBlockSortThreads), 0, s, a,
                        om, (int)mp.t_ins, (int)mp.block_keys);
     return hipGetLastError();
 }
@@ -313,7 +369,7 @@ hipError_t round_t(const KeyDesc& kd, const MergePlan& mp, const MergeRoundArgs&
     const int64_t grid = g.pairs * g.tpp;
     if (grid > 0x7fffffffLL)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((merge_round_kernel<KB, VB, TILE>), dim3((unsigned)grid), dim3(kMergeThreads), 0, s, a, om,
+    hipLaunchKernelGGL((merge_round_kernel<KB, VB, TILE>), dim3((unsigned)grid), dim3(kRoundThreads), 0, s, a, om,
                        g);
     (void)mp;
     return hipGetLastError();
@@ -323,8 +379,9 @@ hipError_t round_t(const KeyDesc& kd, const MergePlan& mp, const MergeRoundArgs&
 
 uint64_t merge_block_capacity(int kb, int vb)
 {
-    (void)vb;
-    return kb == 4 ? (uint64_t)block_cap<4>() : (uint64_t)block_cap<8>();
+    if (kb == 4)
+        return vb ? (uint64_t)block_cap<4, 4>() : (uint64_t)block_cap<4, 0>();
+    return vb ? (uint64_t)block_cap<8, 4>() : (uint64_t)block_cap<8, 0>();
 }
 
 static int round_tile_rt(int kb, int vb) { return (kb + vb) <= 8 ? 4096 : 2048; }
@@ -393,15 +450,15 @@ hipError_t launch_merge_partition(const KeyDesc& kd, const MergePlan& mp, const 
     const int64_t total = g.pairs * (g.tpp + 1);
     if ((uint64_t)total > mp.max_parts + 1)
         return hipErrorInvalidValue;  // partition buffer sized for a different round shape
-    const int64_t grid = (total + kMergeThreads - 1) / kMergeThreads;
+    const int64_t grid = (total + kPartitionThreads - 1) / kPartitionThreads;
     if (grid == 0)
         return hipSuccess;
     if (kd.bytes == 4) {
         OrderMap<uint32_t> om{(uint32_t)kd.flip, (uint32_t)kd.neg, (uint32_t)kd.desc};
-        hipLaunchKernelGGL((merge_partition_kernel<4>), dim3((unsigned)grid), dim3(kMergeThreads), 0, s, a, om, g);
+        hipLaunchKernelGGL((merge_partition_kernel<4>), dim3((unsigned)grid), dim3(kPartitionThreads), 0, s, a, om, g);
     } else {
         OrderMap<uint64_t> om{kd.flip, kd.neg, kd.desc};
-        hipLaunchKernelGGL((merge_partition_kernel<8>), dim3((unsigned)grid), dim3(kMergeThreads), 0, s, a, om, g);
+        hipLaunchKernelGGL((merge_partition_kernel<8>), dim3((unsigned)grid), dim3(kPartitionThreads), 0, s, a, om, g);
     }
     return hipGetLastError();
 }
