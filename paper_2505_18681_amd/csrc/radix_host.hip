@@ -217,13 +217,14 @@ hipError_t launch_radix_pass(const KeyDesc& kd, int val_bytes, int bits, RadixSh
     return e;
 }
 
-// The long segments of a batch (around 1e5 to 4e6 keys each) do better with
-// 12288-key tiles than with the single-array default for 4-byte keys
-// (measured on the 100k-array batch: 16.25 vs 16.55 ms).
+// Tile shapes of the long segments of a batch (around 1e5 to 4e6 keys each),
+// measured on the 100k-array batch: keys-only 4-byte keys take the
+// single-array default, 768 x 24 (15.85 ms against 16.25 ms with 512 x 24 and
+// 16.55 ms with 1024 x 16); pairs keep 8-wave tiles.
 RadixShape seg_default_shape(int key_bytes, int val_bytes)
 {
     if (key_bytes == 4)
-        return val_bytes == 4 ? RadixShape{512, 16} : RadixShape{512, 24};
+        return val_bytes == 0 ? RadixShape{768, 24} : (val_bytes == 4 ? RadixShape{512, 16} : RadixShape{512, 24});
     return val_bytes == 4 ? RadixShape{512, 24} : RadixShape{512, 16};
 }
 

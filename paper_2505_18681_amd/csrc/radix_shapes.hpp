@@ -52,6 +52,6 @@ constexpr RadixShape kRadixFallbackShape{256, 8};
 
 // Tile shapes of the segmented pass (8-bit digits, 32-bit look-back words),
 // compiled where they fit in LDS.
-#define EVOSORT_SEG_SHAPES(X) X(512, 24) X(1024, 16) X(512, 16) X(256, 16) X(256, 8)
+#define EVOSORT_SEG_SHAPES(X) X(512, 24) X(1024, 16) X(512, 16) X(256, 16) X(256, 8) X(768, 24) X(768, 12)
 
 }  // namespace evosort

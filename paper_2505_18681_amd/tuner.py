@@ -187,7 +187,7 @@ def run_ga(space: GeneSpace, fitness: Callable[[tuple], float], *, seed: int = 4
 RADIX_SHAPES = ((0, 0), (256, 8), (256, 12), (256, 16), (256, 24), (256, 32), (256, 48), (512, 8), (512, 16),
                 (512, 24), (512, 32), (768, 12), (768, 16), (768, 20), (768, 24), (1024, 8), (1024, 12), (1024, 16),
                 (1024, 20))
-SEG_SHAPES = ((512, 24), (1024, 16), (512, 16), (256, 16), (256, 8))
+SEG_SHAPES = ((0, 0), (512, 24), (768, 24), (768, 12), (1024, 16), (512, 16), (256, 16), (256, 8))
 
 
 def sort_space() -> GeneSpace:
