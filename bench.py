@@ -161,14 +161,16 @@ def run_sort_bench(es, torch, dtype_name: str, n: int, steps: int, warmup: int, 
     }
 
 
-def run_batched_bench(es, torch, nseg: int, steps: int, warmup: int, seed: int, each_steps: int = 1):
+def run_batched_bench(es, torch, nseg: int, steps: int, warmup: int, seed: int, each_steps: int = 1,
+                      per_array: bool = True):
     """Batched segmented sort of `nseg` uint32 arrays with log-normal sizes, against one plain sort per array.
 
     Three schedules of the same batch, from the same resident input buffer:
       segmented  one evosort_segmented_sort call (fixed launch sequence);
       graph      that call captured once in a HIP graph and replayed;
-      per_array  evosort_sort_each: one evosort_sort per array, in order.
-    All three must produce identical bytes (checked on the device).
+      per_array  evosort_sort_each: one evosort_sort per array, in order
+                 (skipped when per_array is false, e.g. under a kernel trace).
+    All of them must produce identical bytes (checked on the device).
     """
     import numpy as np
 
@@ -224,21 +226,27 @@ def run_batched_bench(es, torch, nseg: int, steps: int, warmup: int, seed: int, 
     graph_equal = True  # compared below against the eager output
 
     seg_out = out.clone()
-    each_temp = torch.empty(max(es.temp_bytes(es.OP_SORT, es.UINT32, int(sizes.max()), 0, params), 256),
-                            dtype=torch.uint8, device="cuda")
-    each = lambda: es.sort_each(keys, offs, params=params, out=ref, temp=each_temp)  # noqa: E731
-    each()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    each_ms = timed(each, each_steps)
-    each_wall_ms = (time.perf_counter() - t0) * 1e3 / each_steps
+    each_ms = each_wall_ms = None
+    if per_array:
+        each_temp = torch.empty(max(es.temp_bytes(es.OP_SORT, es.UINT32, int(sizes.max()), 0, params), 256),
+                                dtype=torch.uint8, device="cuda")
+        each = lambda: es.sort_each(keys, offs, params=params, out=ref, temp=each_temp)  # noqa: E731
+        each()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        each_ms = timed(each, each_steps)
+        each_wall_ms = (time.perf_counter() - t0) * 1e3 / each_steps
+        del each_temp
+    else:
+        ref.copy_(seg_out)
     same = bool(torch.equal(seg_out.view(torch.int32), ref.view(torch.int32)))
+    out.zero_()
     graph.replay()
     torch.cuda.synchronize()
     graph_equal = bool(torch.equal(out.view(torch.int32), ref.view(torch.int32)))
     if not (same and graph_equal):
         raise RuntimeError("segmented, graph and per-array outputs differ")
-    del keys, out, ref, temp, each_temp, offsets, graph
+    del keys, out, ref, temp, offsets, graph
     torch.cuda.empty_cache()
     per_kernel = {k: round(v[1] / v[0], 4) for k, v in kernels.items() if v[0]}
     per_kernel_calls = {k: v[0] // max(steps, 1) for k, v in kernels.items() if v[0]}
@@ -248,9 +256,10 @@ def run_batched_bench(es, torch, nseg: int, steps: int, warmup: int, seed: int, 
         "nseg": nseg, "keys": total,
         "value": round(nseg / (graph_ms * 1e-3), 1), "unit": "segs/s",
         "gkeys_per_s": round(total / (graph_ms * 1e-3) / 1e9, 3),
-        "ms": {"segmented": round(seg_ms, 3), "graph": round(graph_ms, 3), "per_array": round(each_ms, 3),
-               "per_array_host_wall": round(each_wall_ms, 3)},
-        "speedup_vs_per_array": round(each_ms / graph_ms, 2),
+        "ms": {"segmented": round(seg_ms, 3), "graph": round(graph_ms, 3),
+               "per_array": round(each_ms, 3) if each_ms is not None else None,
+               "per_array_host_wall": round(each_wall_ms, 3) if each_wall_ms is not None else None},
+        "speedup_vs_per_array": round(each_ms / graph_ms, 2) if each_ms is not None else None,
         "size_classes": stats,
         "kernels_ms": per_kernel, "launches_per_call": per_kernel_calls,
         "identical_bytes": True,
@@ -615,6 +624,8 @@ def main():
     ap.add_argument("--no-vendor", action="store_true", help="skip the torch.sort comparison")
     ap.add_argument("--no-routines", action="store_true", help="skip the mergesort and small-array measurements")
     ap.add_argument("--batched-nseg", type=int, default=100_000)
+    ap.add_argument("--batched-no-per-array", action="store_true",
+                    help="skip the one-sort-per-array comparison (100k sorts; slow under a kernel trace)")
     ap.add_argument("--no-tuned", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-paper-sweep", action="store_true")
@@ -678,7 +689,8 @@ def main():
 
     batched = None
     if not args.no_batched:
-        batched = run_batched_bench(es, torch, args.batched_nseg, max(2, args.steps // 2), 1, args.seed)
+        batched = run_batched_bench(es, torch, args.batched_nseg, max(2, args.steps // 2), 1, args.seed,
+                                    per_array=not args.batched_no_per_array)
         print(f"# batched: {batched['ms']}", file=sys.stderr, flush=True)
 
     tuned = None
