@@ -103,6 +103,32 @@ struct BlockRec<KB, 0> {
     static __device__ __forceinline__ W top() { return ~(W)0; }
 };
 
+// A key with its index in a round's input slice.
+template <typename U>
+struct KeyIdx;
+template <>
+struct KeyIdx<uint32_t> {
+    uint64_t w;  // key << 32 | index
+    static __device__ __forceinline__ KeyIdx make(uint32_t key, uint32_t idx) { return {((uint64_t)key << 32) | idx}; }
+    static __device__ __forceinline__ uint32_t key(const KeyIdx& r) { return (uint32_t)(r.w >> 32); }
+    static __device__ __forceinline__ uint32_t idx(const KeyIdx& r) { return (uint32_t)r.w; }
+    static __device__ __forceinline__ bool less(const KeyIdx& a, const KeyIdx& b) { return a.w < b.w; }
+    static __device__ __forceinline__ KeyIdx top() { return {~0ull}; }
+};
+template <>
+struct KeyIdx<uint64_t> {
+    uint64_t k;
+    uint32_t i;
+    static __device__ __forceinline__ KeyIdx make(uint64_t key, uint32_t idx) { return {key, idx}; }
+    static __device__ __forceinline__ uint64_t key(const KeyIdx& r) { return r.k; }
+    static __device__ __forceinline__ uint32_t idx(const KeyIdx& r) { return r.i; }
+    static __device__ __forceinline__ bool less(const KeyIdx& a, const KeyIdx& b)
+    {
+        return a.k < b.k || (a.k == b.k && a.i < b.i);
+    }
+    static __device__ __forceinline__ KeyIdx top() { return {~0ull, 0xffffffffu}; }
+};
+
 // Keys per block-sort workgroup: 4096, or 2048 for 16-byte records.
 template <int KB, int VB>
 constexpr int block_cap()
@@ -133,17 +159,69 @@ __device__ __forceinline__ void merge_run(const T* src, int a0, int na, int b0, 
     T ha = i < na ? src[pad16(a0 + i)] : top;
     T hb = j < nb ? src[pad16(b0 + j)] : top;
     for (int o = k; o < k_end; ++o) {
+        // branch-free step: emit the smaller head, refill it with one read
         const bool take_a = j >= nb || (i < na && !less(hb, ha));
-        if (take_a) {
-            emit(o, ha, a0 + i);
-            ++i;
-            ha = i < na ? src[pad16(a0 + i)] : top;
-        } else {
-            emit(o, hb, b0 + j);
-            ++j;
-            hb = j < nb ? src[pad16(b0 + j)] : top;
+        emit(o, take_a ? ha : hb, take_a ? a0 + i : b0 + j);
+        i += take_a ? 1 : 0;
+        j += take_a ? 0 : 1;
+        const int next = take_a ? a0 + i : b0 + j;
+        const bool more = take_a ? i < na : j < nb;
+        const T x = src[pad16(more ? next : a0)];  // a0 is always a valid index
+        const T nx = more ? x : top;
+        ha = take_a ? nx : ha;
+        hb = take_a ? hb : nx;
+    }
+}
+
+// Outputs [k, k_end) (at most PER of them) of the merge of the sorted runs A
+// (indices a0 .. a0 + na - 1) and B (b0 .. b0 + nb - 1), read with load(index),
+// with the same tie rule as merge_run.  After the merge-path search the thread
+// loads PER elements of each run from where its outputs start (independent
+// reads), and keeps the PER smallest of them: for ascending x and y,
+// min(x[q], y[PER-1-q]) are the PER smallest and form a bitonic sequence, which
+// a bitonic merging network puts in order.  All in registers, no branches.
+template <int PER, typename T, typename Load, typename Less, typename Emit>
+__device__ __forceinline__ void merge_window(Load load, int a0, int na, int b0, int nb, int k, int k_end,
+                                             const T& top, Less less, Emit emit)
+{
+    static_assert(PER >= 2 && (PER & (PER - 1)) == 0, "a power of two");
+    int lo = k - nb > 0 ? k - nb : 0;
+    int hi = k < na ? k : na;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (!less(load(b0 + k - 1 - mid), load(a0 + mid)))
+            lo = mid + 1;  // A[mid] goes before B[k-1-mid]
+        else
+            hi = mid;
+    }
+    const int i0 = lo, j0 = k - lo;
+    T x[PER], y[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        x[q] = i0 + q < na ? load(a0 + i0 + q) : top;
+        y[q] = j0 + q < nb ? load(b0 + j0 + q) : top;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const T v = y[PER - 1 - q];
+        x[q] = less(v, x[q]) ? v : x[q];  // A's element on ties
+    }
+#pragma unroll
+    for (int st = PER / 2; st >= 1; st >>= 1) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if ((q & st) == 0) {
+                const T u = x[q], v = x[q + st];
+                const bool sw = less(v, u);
+                x[q] = sw ? v : u;
+                x[q + st] = sw ? u : v;
+            }
         }
     }
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+        if (k + q < k_end)
+            emit(k + q, x[q]);
 }
 
 template <int KB, int VB>
@@ -189,23 +267,35 @@ __global__ __launch_bounds__(kBlockSortThreads) void merge_block_sort_kernel(Mer
     __syncthreads();
 
     // Pairwise merges inside the block, run length doubling from t_ins; on
-    // equal records the left run's goes first.
-    const int per = (nb + kBlockSortThreads - 1) / kBlockSortThreads;
+    // equal records the left run's goes first.  Thread t owns outputs
+    // [t*PER, (t+1)*PER) of every level.
+    constexpr int PER = CAP / kBlockSortThreads;
+    const auto less = [](const W& x, const W& y) { return R::less(x, y); };
     int cur = 1;
     for (int L = t_ins; L < nb; L *= 2) {
         const W* src = buf[cur];
         W* dst = buf[cur ^ 1];
-        int o = threadIdx.x * per;
-        const int o_end = o + per < nb ? o + per : nb;
-        while (o < o_end) {  // the thread's outputs may span pairs of runs
-            const int s = (o / (2 * L)) * (2 * L);
-            const int mid = s + L < nb ? s + L : nb;
-            const int e = s + 2 * L < nb ? s + 2 * L : nb;
-            const int stop = o_end < e ? o_end : e;
-            merge_run<W>(src, s, mid - s, mid, e - mid, o - s, stop - s, R::top(),
-                         [](const W& x, const W& y) { return R::less(x, y); },
-                         [&](int q, const W& r, int) { dst[pad16(s + q)] = r; });
-            o = stop;
+        int o = threadIdx.x * PER;
+        const int o_end = o + PER < nb ? o + PER : nb;
+        if ((2 * L) % PER == 0) {
+            // a thread's outputs lie in one pair of runs
+            if (o < o_end) {
+                const int s = (o / (2 * L)) * (2 * L);
+                const int mid = s + L < nb ? s + L : nb;
+                const int e = s + 2 * L < nb ? s + 2 * L : nb;
+                merge_window<PER, W>([&](int i) { return src[pad16(i)]; }, s, mid - s, mid, e - mid, o - s,
+                                     o_end - s, R::top(), less, [&](int q, const W& r) { dst[pad16(s + q)] = r; });
+            }
+        } else {
+            while (o < o_end) {  // the thread's outputs may span pairs of runs
+                const int s = (o / (2 * L)) * (2 * L);
+                const int mid = s + L < nb ? s + L : nb;
+                const int e = s + 2 * L < nb ? s + 2 * L : nb;
+                const int stop = o_end < e ? o_end : e;
+                merge_run<W>(src, s, mid - s, mid, e - mid, o - s, stop - s, R::top(), less,
+                             [&](int q, const W& r, int) { dst[pad16(s + q)] = r; });
+                o = stop;
+            }
         }
         __syncthreads();
         cur ^= 1;
@@ -322,14 +412,24 @@ __global__ __launch_bounds__(kRoundThreads) void merge_round_kernel(MergeRoundAr
     {
         const int o = threadIdx.x * PER;
         const int o_end = o + PER < cnt ? o + PER : cnt;
-        if (o < o_end)
+        if (o < o_end) {
             // ties favour the A run: an A element goes first unless B's is smaller
-            merge_run<U>(s_in, 0, ca, ca, cb, o, o_end, (U)~(U)0, [](U x, U y) { return x < y; },
-                         [&](int q, U key, int from) {
-                             s_out[pad16(q)] = key;
-                             if constexpr (VB != 0)
-                                 v_out[pad16(q)] = v_in[from];
-                         });
+            if constexpr (VB == 0) {
+                merge_window<PER, U>([&](int i) { return s_in[pad16(i)]; }, 0, ca, ca, cb, o, o_end, (U)~(U)0,
+                                     [](U x, U y) { return x < y; }, [&](int q, U key) { s_out[pad16(q)] = key; });
+            } else {
+                // (key, slice index) pairs: A's indices are below B's, so the
+                // order of the pairs is the merge order with A first on ties,
+                // and the index finds the value
+                using KI = KeyIdx<U>;
+                merge_window<PER, KI>([&](int i) { return KI::make(s_in[pad16(i)], (uint32_t)i); }, 0, ca, ca, cb, o,
+                                      o_end, KI::top(), [](const KI& x, const KI& y) { return KI::less(x, y); },
+                                      [&](int q, const KI& r) {
+                                          s_out[pad16(q)] = KI::key(r);
+                                          v_out[pad16(q)] = v_in[KI::idx(r)];
+                                      });
+            }
+        }
     }
     __syncthreads();
     U* keys_out = reinterpret_cast<U*>(a.keys_out);
