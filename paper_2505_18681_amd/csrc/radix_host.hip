@@ -102,7 +102,10 @@ hipError_t launch_radix_histogram_tiles(const KeyDesc& kd, const void* keys, int
         return hipSuccess;
     const int copies = kHistThreads / kWave;
     const size_t lds = ((size_t)copies * passes + 1) * 256 * 4;
-    const uint32_t grid = tiles < 4096 ? tiles : 4096;
+    // Workgroups stride over the tiles; 16384 of them (about 3 tiles each at
+    // 1e9 int32 keys) beat 4096 and 8192 (1e9 int32: 1.06 ms against 1.10 and
+    // 1.07) despite four times the global flushes of 4096.
+    const uint32_t grid = tiles < 16384 ? tiles : 16384;
     auto* h = reinterpret_cast<unsigned long long*>(hist);
 #define EVOSORT_HT(KB, P, ST, U)                                                                                 \
     do {                                                                                                       \
