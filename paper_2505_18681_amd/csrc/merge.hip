@@ -18,16 +18,18 @@
 //                            out coalesced.
 //
 // Every merge inside LDS (the block's levels and a round's tile) is split the
-// same way: each thread owns a run of consecutive outputs, finds where its run
-// starts on both inputs by one merge-path search, then merges its run
-// sequentially with the two heads in registers: one LDS read and one write
-// per element instead of a binary search per element.  LDS arrays are padded
-// by one element every 16, so that the threads' runs start in different
-// banks.
+// same way: each thread owns a run of consecutive outputs and finds where its
+// run starts on both inputs by one merge-path search; it then loads that many
+// elements of both inputs from there into registers and keeps the smallest
+// with a bitonic merging network (merge_window), or, where a block level's
+// pairs of runs are not a multiple of the thread's run, merges sequentially
+// with both heads in registers (merge_run).  LDS arrays are padded by one
+// element every 16, so that the threads' runs start in different banks.
 //
-// Stability: inside a block, records carry their position, so all records
-// are distinct and every merge is exact.  Across blocks, the merge takes the
-// left run's element first on equal keys.
+// Stability: with values, block records carry their position, so all records
+// are distinct and every merge is exact; keys-only blocks rank chunk mates by
+// (key, index) and merge left-first, which leaves equal keys in input order.
+// Across blocks, the merge takes the left run's element first on equal keys.
 #include "common.hpp"
 #include "merge.hpp"
 
@@ -453,6 +455,8 @@ template <int KB, int VB>
 hipError_t block_sort_t(const KeyDesc& kd, const MergePlan& mp, const MergeBlockArgs& a, hipStream_t s)
 {
     using U = typename KeyWord<KB>::U;
+    if (mp.block_keys > (uint64_t)block_cap<KB, VB>() || mp.block_keys == 0)
+        return hipErrorInvalidValue;  // a plan made for another value width
     OrderMap<U> om{(U)kd.flip, (U)kd.neg, (U)kd.desc};
     hipLaunchKernelGGL((merge_block_sort_kernel<KB, VB>), dim3((unsigned)mp.blocks), dim3(kBlockSortThreads), 0, s, a,
                        om, (int)mp.t_ins, (int)mp.block_keys);
@@ -464,6 +468,8 @@ hipError_t round_t(const KeyDesc& kd, const MergePlan& mp, const MergeRoundArgs&
 {
     using U = typename KeyWord<KB>::U;
     constexpr int TILE = round_tile<KB>(VB);
+    if (mp.tile_out != (uint32_t)TILE)
+        return hipErrorInvalidValue;  // the partition was cut for another tile
     OrderMap<U> om{(U)kd.flip, (U)kd.neg, (U)kd.desc};
     const RoundGeom g = round_geom(a.n, a.run, TILE);
     const int64_t grid = g.pairs * g.tpp;
@@ -471,7 +477,6 @@ hipError_t round_t(const KeyDesc& kd, const MergePlan& mp, const MergeRoundArgs&
         return hipErrorInvalidValue;
     hipLaunchKernelGGL((merge_round_kernel<KB, VB, TILE>), dim3((unsigned)grid), dim3(kRoundThreads), 0, s, a, om,
                        g);
-    (void)mp;
     return hipGetLastError();
 }
 
