@@ -219,7 +219,7 @@ evosort_status make_plan(int op, int dtype, int64_t n, uint32_t value_bytes, con
     P->debug_flags = p.debug_flags;
     P->t_ins = p.insertion_threshold;
     P->shape = p.block_threads ? RadixShape{(int)p.block_threads, (int)p.items_per_thread}
-                               : radix_default_shape(kb, vb, (int)p.digit_bits);
+                               : radix_default_shape_for(kb, vb, (int)p.digit_bits, n);
     const int64_t cap = small_sort_capacity(kb, vb);
     P->info.small_capacity = (uint64_t)cap;
     P->info.digit_bits = p.digit_bits;

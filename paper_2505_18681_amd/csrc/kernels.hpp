@@ -69,6 +69,8 @@ struct RadixShape {
 // Default tile shape for (key bytes, value bytes, digit bits): the preferred
 // shape where it fits in LDS, else the fallback shape.
 RadixShape radix_default_shape(int key_bytes, int val_bytes, int bits);
+// The default shape for an array of n keys: smaller tiles for short arrays.
+RadixShape radix_default_shape_for(int key_bytes, int val_bytes, int bits, int64_t n);
 // Whether a single-sweep pass kernel exists for these parameters.
 bool radix_pass_available(int key_bytes, int val_bytes, int bits, RadixShape shape, int status_bytes);
 hipError_t launch_radix_pass(const KeyDesc& kd, int val_bytes, int bits, RadixShape shape, int status_bytes,
