@@ -260,3 +260,19 @@ def test_graph_capture_replays_with_new_inputs(path, op):
         check(keys, vals, f"{path} {op} replay {r}")
         x = to_dev(workloads.uniform(np.int32, 40_000, r))  # eager library work between replays
         assert oracle.first_unsorted(to_np(es.sort(x))) == -1
+
+
+@pytest.mark.parametrize("dt", [np.int32, np.float64])
+def test_pass0_from_tile_prefixes(dt):
+    """From 256 tiles on, pass 0 takes its offsets from a scan of the histogram's per-tile counts instead of
+    the look-back; small tiles reach that count at a test size (below it the look-back serves pass 0)."""
+    import torch
+
+    es = require_gpu()
+    p = es.default_params(algo=es.ALGO_RADIX, fallback_threshold=0, block_threads=256, items_per_thread=8)
+    tdt = torch.int32 if dt == np.int32 else torch.float64
+    for n in (300_001, 2048 * 256 - 1):  # 147 tiles (look-back), 256 tiles (tile prefixes)
+        assert es.plan(es.OP_SORT, es.dtype_code(tdt), n, 0, p)["tiles"] == (n + 2047) // 2048
+        keys = workloads.float_mix(dt, n, 12) if dt == np.float64 else workloads.uniform(dt, n, 12)
+        keys[::5] = keys[3]
+        check_sort_full(es, keys, p, f"tile prefixes {np.dtype(dt).name} n={n}")
