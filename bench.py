@@ -116,15 +116,17 @@ def run_sort_bench(es, torch, dtype_name: str, n: int, steps: int, warmup: int, 
 
     es.profile_reset()
     es.profile_enable(True)
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # one event between consecutive steps: the whole run and every step are timed on the same stream
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
-    start.record(stream)
-    for _ in range(steps):
+    marks[0].record(stream)
+    for i in range(steps):
         es.sort(keys, params=params, out=out, temp=temp)
-    stop.record(stream)
+        marks[i + 1].record(stream)
     torch.cuda.synchronize()
     es.profile_enable(False)
-    total_ms = start.elapsed_time(stop)
+    total_ms = marks[0].elapsed_time(marks[-1])
+    step_ms = sorted(marks[i].elapsed_time(marks[i + 1]) for i in range(steps))
     kernels = es.profile_collect()
     es.profile_reset()
 
@@ -158,6 +160,8 @@ def run_sort_bench(es, torch, dtype_name: str, n: int, steps: int, warmup: int, 
         "tile": [info["block_threads"], info["items_per_thread"]],
         "status_bytes": info["status_bytes"],
         "gen_s": gen_s,
+        "step_ms": {"min": round(step_ms[0], 4), "median": round(step_ms[len(step_ms) // 2], 4),
+                    "max": round(step_ms[-1], 4)} if step_ms else None,
     }
 
 
@@ -667,6 +671,7 @@ def main():
             "workload": f"int64 uniform {args.n:.0e} keys-only LSD radix sort, {sec['passes']} passes of "
                         f"{args.digit_bits}-bit digits",
             "value": round(sec["gkeys_per_s"], 4), "unit": "Gkeys/s", "ms_per_step": round(sec["ms_per_step"], 4),
+            "step_ms": sec["step_ms"],
             "roofline": {"bound": "hbm", "achieved": round(sec["pass_gbs"], 1) if sec["pass_gbs"] else None,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(sec["pass_gbs"] / HBM_PEAK_GBS, 4) if sec["pass_gbs"] else None},
@@ -739,6 +744,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(main_res["ms_per_step"], 4),
+        "step_ms": main_res["step_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
