@@ -114,11 +114,24 @@ hipError_t timed(const char* name, hipStream_t s, F&& launch)
         a = P.get_event();
         b = P.get_event();
     }
-    if (!a || !b)
+    auto give_back = [&] {
+        std::lock_guard<std::mutex> g(P.mu);
+        if (a)
+            P.pool.push_back(a);
+        if (b)
+            P.pool.push_back(b);
+    };
+    if (!a || !b || hipEventRecord(a, s) != hipSuccess) {
+        (void)hipGetLastError();
+        give_back();  // this launch goes untimed
         return launch();
-    hipEventRecord(a, s);
-    hipError_t e = launch();
-    hipEventRecord(b, s);
+    }
+    const hipError_t e = launch();
+    if (hipEventRecord(b, s) != hipSuccess) {
+        (void)hipGetLastError();
+        give_back();
+        return e;
+    }
     std::lock_guard<std::mutex> g(P.mu);
     P.pending.push_back({name, a, b});
     return e;
@@ -172,7 +185,7 @@ void default_params(evosort_params* p)
     p->algo = EVOSORT_ALGO_AUTO;
     p->digit_bits = 8;
     p->insertion_threshold = kDefaultInsertion;
-    p->fallback_threshold = (uint64_t)kSmallCapacity4;
+    p->fallback_threshold = (uint64_t)kSmallCapacity;
     p->block_threads = 0;
     p->items_per_thread = 0;
     p->spin_limit = 0;

@@ -21,9 +21,11 @@ struct SmallShape {
     int items;
 };
 constexpr int kSmallShapeCount = 6;
-constexpr SmallShape kSmallShapes4[kSmallShapeCount] = {{64, 8}, {256, 4}, {256, 8}, {512, 8}, {1024, 8}, {1024, 16}};
-constexpr SmallShape kSmallShapes8[kSmallShapeCount] = {{64, 8}, {256, 4}, {256, 8}, {512, 8}, {1024, 8}, {512, 16}};
-static_assert(1024 * 16 == kSmallCapacity4 && 512 * 16 == kSmallCapacity8, "the largest shape holds the capacity");
+// 4-byte keys, and 8-byte keys without values
+constexpr SmallShape kSmallShapes[kSmallShapeCount] = {{64, 8}, {256, 4}, {256, 8}, {512, 8}, {1024, 8}, {1024, 16}};
+// 8-byte keys with values or indices (registers: 16 keys and 16 values per thread need 512 threads)
+constexpr SmallShape kSmallShapes8V[kSmallShapeCount] = {{64, 8}, {256, 4}, {256, 8}, {512, 8}, {1024, 8}, {512, 16}};
+static_assert(1024 * 16 == kSmallCapacity && 512 * 16 == kSmallCapacity8V, "the largest shape holds the capacity");
 
 // Keys and values share the staging area unless that would not fit in LDS.
 template <int KB, int VB, int THREADS, int ITEMS>
@@ -58,7 +60,7 @@ hipError_t launch_shape(const KeyDesc& kd, const SmallSortArgs& a, hipStream_t s
 template <int KB, int VB, int I>
 hipError_t launch_t(const KeyDesc& kd, const SmallSortArgs& a, hipStream_t s)
 {
-    constexpr SmallShape sh = KB == 4 ? kSmallShapes4[I] : kSmallShapes8[I];
+    constexpr SmallShape sh = KB == 8 && VB != 0 ? kSmallShapes8V[I] : kSmallShapes[I];
     if constexpr (I + 1 < kSmallShapeCount) {
         if (a.n > (int64_t)sh.threads * sh.items)
             return launch_t<KB, VB, I + 1>(kd, a, s);
@@ -70,8 +72,7 @@ hipError_t launch_t(const KeyDesc& kd, const SmallSortArgs& a, hipStream_t s)
 
 int64_t small_sort_capacity(int key_bytes, int val_bytes)
 {
-    (void)val_bytes;
-    return key_bytes == 4 ? kSmallCapacity4 : kSmallCapacity8;
+    return key_bytes == 8 && val_bytes != 0 ? kSmallCapacity8V : kSmallCapacity;
 }
 
 hipError_t launch_small_sort(const KeyDesc& kd, int val_bytes, const SmallSortArgs& a, hipStream_t s)

@@ -10,8 +10,8 @@ namespace evosort {
 
 // Largest n the one-workgroup sort takes: the whole array (keys and values,
 // or indices) stays in one workgroup's registers and LDS for every pass.
-constexpr int kSmallCapacity4 = 16384;
-constexpr int kSmallCapacity8 = 8192;
+constexpr int kSmallCapacity = 16384;    // 4-byte keys; 8-byte keys without values
+constexpr int kSmallCapacity8V = 8192;   // 8-byte keys with values or indices
 
 enum SmallMode : int { SMALL_MODE_KEYS = 0, SMALL_MODE_PAIRS = 1, SMALL_MODE_ARGSORT = 2 };
 
