@@ -46,6 +46,17 @@
  *     output and temp buffers returns EVOSORT_ERR_INVALID_ARG.
  *   - All functions are safe to call from several host threads as long as
  *     their buffers are distinct.
+ *   - Device-side errors.  A radix pass whose bounded look-back wait runs out
+ *     (spin_limit) and a batch whose segment offsets break their rules fail
+ *     after the call that enqueued them has returned.  Such a failure is
+ *     recorded in that call's temp and in a host-visible word of the device,
+ *     and reported once, by whichever comes first:
+ *       - evosort_check_device_error on that call's temp (synchronizes);
+ *       - the next evosort_sort, _sort_pairs, _argsort, _radix_pass,
+ *         _segmented_sort(_pairs) or _sort_each call on the same device made
+ *         after the failing kernel ran: it returns EVOSORT_ERR_DEVICE_TIMEOUT
+ *         (EVOSORT_ERR_INVALID_ARG for bad offsets) and enqueues nothing.
+ *     The outputs of the failed call are undefined.
  */
 #ifndef EVOSORT_H_
 #define EVOSORT_H_
@@ -106,6 +117,9 @@ typedef enum evosort_path {
 #define EVOSORT_DEBUG_WITHHOLD_TILE0 0x1u /* radix tile 0 never publishes its counts: later
                                             tiles run out of spin_limit and the call reports
                                             EVOSORT_ERR_DEVICE_TIMEOUT through the error word */
+#define EVOSORT_DEBUG_WIDE_STATUS 0x2u    /* 64-bit look-back words at every n (normally only from
+                                            n = 2^30 on), so that tests reach those kernels at
+                                            small sizes; results are unchanged */
 
 /*
  * Parameters.  Always initialise with evosort_default_params() and then change
@@ -422,11 +436,19 @@ const char *evosort_status_string(int status);
 /* hipError_t behind the last EVOSORT_ERR_HIP on this host thread (0 if none). */
 int evosort_last_hip_error(void);
 
+/* Identity of the built library: the first 16 hex digits of the SHA-256 of
+ * its source files (every file of the package's csrc/ directory and of
+ * include/, in name order, each as its relative path, a NUL byte and its
+ * bytes), fixed when the library was compiled.  Static string. */
+const char *evosort_build_id(void);
+
 /*
- * Synchronize `stream` and read the device error word a radix or segmented
+ * Synchronize `stream` and read the device error word a sort or segmented
  * call left in `temp`: EVOSORT_OK, EVOSORT_ERR_DEVICE_TIMEOUT if a look-back
  * wait ran out of spin_limit, or EVOSORT_ERR_INVALID_ARG if segment offsets
- * broke their rules.  temp/temp_bytes as passed to that call.
+ * broke their rules.  temp/temp_bytes as passed to that call (every routine
+ * clears the word when it starts, so a temp reused by a later call reports
+ * that call).  An error found here is not reported again by the next call.
  */
 evosort_status evosort_check_device_error(const void *temp, size_t temp_bytes, void *stream);
 

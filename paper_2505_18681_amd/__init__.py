@@ -47,6 +47,7 @@ PATH_NAMES = {0: "copy", 1: "small", 2: "radix", 3: "merge"}
 (OK, ERR_INVALID_ARG, ERR_UNSUPPORTED_DTYPE, ERR_UNSUPPORTED_PARAM, ERR_TEMP_TOO_SMALL, ERR_HIP, ERR_DEVICE_TIMEOUT,
  ERR_OVER_BUDGET, ERR_PENDING) = range(9)
 DEBUG_WITHHOLD_TILE0 = 0x1
+DEBUG_WIDE_STATUS = 0x2
 
 EXPORTED = (
     "evosort_default_params", "evosort_temp_bytes", "evosort_plan", "evosort_sort", "evosort_sort_pairs",
@@ -57,7 +58,7 @@ EXPORTED = (
     "evosort_segmented_capacity", "evosort_segmented_stats", "evosort_sort_each",
     "evosort_server_default_config", "evosort_server_create", "evosort_server_destroy", "evosort_server_submit",
     "evosort_server_result", "evosort_server_wait", "evosort_server_copy_out", "evosort_server_times",
-    "evosort_server_release", "evosort_server_drain", "evosort_server_get_stats",
+    "evosort_server_release", "evosort_server_drain", "evosort_server_get_stats", "evosort_build_id",
 )
 
 
@@ -142,6 +143,8 @@ _lib.evosort_merge_round.argtypes = [_i32, _vp, _vp, _vp, _vp, _u32, _i64, _i64,
 _lib.evosort_status_string.argtypes = [_i32]
 _lib.evosort_status_string.restype = ctypes.c_char_p
 _lib.evosort_last_hip_error.argtypes = []
+_lib.evosort_build_id.argtypes = []
+_lib.evosort_build_id.restype = ctypes.c_char_p
 _lib.evosort_check_device_error.argtypes = [_vp, _sz, _vp]
 _lib.evosort_profile_enable.argtypes = [_i32]
 _lib.evosort_profile_enable.restype = None
@@ -193,6 +196,11 @@ class EvosortError(RuntimeError):
 
 def status_string(status: int) -> str:
     return _lib.evosort_status_string(int(status)).decode()
+
+
+def build_id() -> str:
+    """Hash of the sources the loaded library was compiled from (``evosort_build_id``)."""
+    return _lib.evosort_build_id().decode()
 
 
 def _check(where: str, st: int):
@@ -274,15 +282,36 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
 
 
+def _finish(where: str, device, tmp, allocated, stream, check: bool):
+    """After a call enqueued on ``stream``: tensors this module allocated on the current stream are marked
+    as used by ``stream`` (so PyTorch's allocator does not hand their memory out again before that stream's
+    kernels end), and with ``check`` the call's device error word is read (this synchronizes ``stream``)
+    and a device-side failure raises."""
+    torch = _torch()
+    if stream is not None and stream.cuda_stream != torch.cuda.current_stream(device).cuda_stream:
+        for t in (tmp, *allocated):
+            if t is not None and t.numel():
+                t.record_stream(stream)
+    if check:
+        with torch.cuda.device(device):
+            _check(where, _lib.evosort_check_device_error(_ptr(tmp), tmp.numel(), _stream(device, stream)))
+
+
 # ---------------------------------------------------------------- the sorts --
-def sort(keys, *, params: Params | None = None, out=None, stream=None, temp=None):
-    """Keys in ascending order (stable; floats in IEEE totalOrder).  ``out=keys`` sorts in place."""
+def sort(keys, *, params: Params | None = None, out=None, stream=None, temp=None, check: bool = False):
+    """Keys in ascending order (stable; floats in IEEE totalOrder).  ``out=keys`` sorts in place.
+
+    The call returns once the work is enqueued on ``stream`` (default: PyTorch's current stream).  With
+    ``check=True`` it waits for the work and raises :class:`EvosortError` on a device-side failure; without,
+    such a failure is raised by the next library call made after it happened."""
     torch = _torch()
     keys = _key_tensor(keys)
     code = dtype_code(keys.dtype)
     n = keys.numel()
+    allocated = []
     if out is None:
         out = torch.empty_like(keys)
+        allocated.append(out)
     _key_tensor(out, "out")
     if out.dtype != keys.dtype or out.numel() != n:
         raise ValueError("out must match keys in dtype and length")
@@ -291,12 +320,14 @@ def sort(keys, *, params: Params | None = None, out=None, stream=None, temp=None
     with torch.cuda.device(keys.device):
         _check("evosort_sort", _lib.evosort_sort(code, _ptr(keys), _ptr(out), n, _ptr(tmp), tmp.numel(),
                                                  _pp(params), _stream(keys.device, stream)))
+    _finish("evosort_sort", keys.device, tmp, allocated, stream, check)
     return out
 
 
 def sort_pairs(keys, values, *, params: Params | None = None, keys_out=None, values_out=None, stream=None,
-               temp=None):
-    """(keys, values) sorted stably by key; values are opaque 4- or 8-byte words."""
+               temp=None, check: bool = False):
+    """(keys, values) sorted stably by key; values are opaque 4- or 8-byte words.  ``stream`` and ``check``
+    as for :func:`sort`."""
     torch = _torch()
     keys = _key_tensor(keys)
     values = _key_tensor(values, "values")
@@ -307,19 +338,26 @@ def sort_pairs(keys, values, *, params: Params | None = None, keys_out=None, val
     vb = values.element_size()
     if vb not in (4, 8):
         raise TypeError("values must be 4- or 8-byte elements")
-    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
-    values_out = torch.empty_like(values) if values_out is None else values_out
+    allocated = []
+    if keys_out is None:
+        keys_out = torch.empty_like(keys)
+        allocated.append(keys_out)
+    if values_out is None:
+        values_out = torch.empty_like(values)
+        allocated.append(values_out)
     need = temp_bytes(OP_SORT_PAIRS, code, n, vb, params)
     tmp = temp if temp is not None else _temp(need, keys.device)
     with torch.cuda.device(keys.device):
         _check("evosort_sort_pairs",
                _lib.evosort_sort_pairs(code, _ptr(keys), _ptr(keys_out), _ptr(values), _ptr(values_out), vb, n,
                                        _ptr(tmp), tmp.numel(), _pp(params), _stream(keys.device, stream)))
+    _finish("evosort_sort_pairs", keys.device, tmp, allocated, stream, check)
     return keys_out, values_out
 
 
-def argsort(keys, *, index_dtype=None, params: Params | None = None, out=None, stream=None, temp=None):
-    """Stable sorting permutation (int64 by default, or int32)."""
+def argsort(keys, *, index_dtype=None, params: Params | None = None, out=None, stream=None, temp=None,
+            check: bool = False):
+    """Stable sorting permutation (int64 by default, or int32).  ``stream`` and ``check`` as for :func:`sort`."""
     torch = _torch()
     keys = _key_tensor(keys)
     code = dtype_code(keys.dtype)
@@ -328,12 +366,16 @@ def argsort(keys, *, index_dtype=None, params: Params | None = None, out=None, s
     if index_dtype not in (torch.int32, torch.int64):
         raise TypeError("index_dtype must be torch.int32 or torch.int64")
     ib = 4 if index_dtype == torch.int32 else 8
-    out = torch.empty(n, dtype=index_dtype, device=keys.device) if out is None else out
+    allocated = []
+    if out is None:
+        out = torch.empty(n, dtype=index_dtype, device=keys.device)
+        allocated.append(out)
     need = temp_bytes(OP_ARGSORT, code, n, ib, params)
     tmp = temp if temp is not None else _temp(need, keys.device)
     with torch.cuda.device(keys.device):
         _check("evosort_argsort", _lib.evosort_argsort(code, _ptr(keys), _ptr(out), ib, n, _ptr(tmp), tmp.numel(),
                                                        _pp(params), _stream(keys.device, stream)))
+    _finish("evosort_argsort", keys.device, tmp, allocated, stream, check)
     return out
 
 
@@ -350,6 +392,7 @@ def radix_histogram(keys, digit_bits: int = 8, *, stream=None):
         _check("evosort_radix_histogram",
                _lib.evosort_radix_histogram(code, _ptr(keys), keys.numel(), digit_bits, _ptr(hist), _ptr(bases),
                                             None, 0, _stream(keys.device, stream)))
+    _finish("evosort_radix_histogram", keys.device, None, [hist, bases], stream, False)
     return hist, bases
 
 
@@ -369,6 +412,7 @@ def radix_pass(keys, values=None, *, pass_index: int, params: Params | None = No
                _lib.evosort_radix_pass(code, _ptr(keys), _ptr(kout), _ptr(values) if vb else None,
                                        _ptr(vout) if vb else None, vb, n, pass_index, _ptr(tmp), tmp.numel(),
                                        _pp(params), _stream(keys.device, stream)))
+    _finish("evosort_radix_pass", keys.device, tmp, [kout, vout], stream, False)
     return kout, vout
 
 
@@ -387,6 +431,7 @@ def merge_block_sort(keys, values=None, *, params: Params | None = None, stream=
                _lib.evosort_merge_block_sort(code, _ptr(keys), _ptr(kout), _ptr(values) if vb else None,
                                              _ptr(vout) if vb else None, vb, n, _pp(params), ctypes.byref(run),
                                              _stream(keys.device, stream)))
+    _finish("evosort_merge_block_sort", keys.device, None, [kout, vout], stream, False)
     return kout, vout, int(run.value)
 
 
@@ -406,6 +451,7 @@ def merge_round(keys, values=None, *, run: int, stream=None):
                _lib.evosort_merge_round(code, _ptr(keys), _ptr(kout), _ptr(values) if vb else None,
                                         _ptr(vout) if vb else None, vb, n, run, _ptr(tmp), tmp.numel(),
                                         _stream(keys.device, stream)))
+    _finish("evosort_merge_round", keys.device, tmp, [kout, vout], stream, False)
     return kout, vout
 
 
@@ -439,7 +485,8 @@ def _offsets_tensor(offsets, device):
     return offsets
 
 
-def segmented_sort(keys, offsets, *, params: Params | None = None, out=None, stream=None, temp=None):
+def segmented_sort(keys, offsets, *, params: Params | None = None, out=None, stream=None, temp=None,
+                   check: bool = False):
     """Each segment keys[offsets[i]:offsets[i+1]] sorted on its own (stable), in one launch sequence.
 
     ``offsets`` is an int64 tensor on the keys' device.  Positions outside
@@ -450,7 +497,10 @@ def segmented_sort(keys, offsets, *, params: Params | None = None, out=None, str
     offsets = _offsets_tensor(offsets, keys.device)
     code = dtype_code(keys.dtype)
     n, nseg = keys.numel(), offsets.numel() - 1
-    out = torch.empty_like(keys) if out is None else out
+    allocated = []
+    if out is None:
+        out = torch.empty_like(keys)
+        allocated.append(out)
     _key_tensor(out, "out")
     if out.dtype != keys.dtype or out.numel() != n:
         raise ValueError("out must match keys in dtype and length")
@@ -459,11 +509,12 @@ def segmented_sort(keys, offsets, *, params: Params | None = None, out=None, str
         _check("evosort_segmented_sort",
                _lib.evosort_segmented_sort(code, _ptr(keys), _ptr(out), n, _ptr(offsets), nseg, _ptr(tmp),
                                            tmp.numel(), _pp(params), _stream(keys.device, stream)))
+    _finish("evosort_segmented_sort", keys.device, tmp, allocated, stream, check)
     return out
 
 
 def segmented_sort_pairs(keys, values, offsets, *, params: Params | None = None, keys_out=None, values_out=None,
-                         stream=None, temp=None):
+                         stream=None, temp=None, check: bool = False):
     """(keys, values) with each segment sorted stably by key, in one launch sequence."""
     torch = _torch()
     keys = _key_tensor(keys)
@@ -476,14 +527,20 @@ def segmented_sort_pairs(keys, values, offsets, *, params: Params | None = None,
     vb = values.element_size()
     if vb not in (4, 8):
         raise TypeError("values must be 4- or 8-byte elements")
-    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
-    values_out = torch.empty_like(values) if values_out is None else values_out
+    allocated = []
+    if keys_out is None:
+        keys_out = torch.empty_like(keys)
+        allocated.append(keys_out)
+    if values_out is None:
+        values_out = torch.empty_like(values)
+        allocated.append(values_out)
     tmp = temp if temp is not None else _temp(segmented_temp_bytes(code, n, nseg, vb, params), keys.device)
     with torch.cuda.device(keys.device):
         _check("evosort_segmented_sort_pairs",
                _lib.evosort_segmented_sort_pairs(code, _ptr(keys), _ptr(keys_out), _ptr(values), _ptr(values_out),
                                                  vb, n, _ptr(offsets), nseg, _ptr(tmp), tmp.numel(), _pp(params),
                                                  _stream(keys.device, stream)))
+    _finish("evosort_segmented_sort_pairs", keys.device, tmp, allocated, stream, check)
     return keys_out, values_out
 
 
@@ -509,12 +566,17 @@ def sort_each(keys, host_offsets, values=None, *, params: Params | None = None, 
     code = dtype_code(keys.dtype)
     offs = np.ascontiguousarray(np.asarray(host_offsets, dtype=np.int64))
     nseg = offs.size - 1
-    out = torch.empty_like(keys) if out is None else out
+    allocated = []
+    if out is None:
+        out = torch.empty_like(keys)
+        allocated.append(out)
     vb = 0
     if values is not None:
         values = _key_tensor(values, "values")
         vb = values.element_size()
-        values_out = torch.empty_like(values) if values_out is None else values_out
+        if values_out is None:
+            values_out = torch.empty_like(values)
+            allocated.append(values_out)
     longest = int(np.max(np.diff(offs))) if nseg > 0 else 0
     op = OP_SORT_PAIRS if vb else OP_SORT
     tmp = temp if temp is not None else _temp(temp_bytes(op, code, longest, vb, params), keys.device)
@@ -524,6 +586,7 @@ def sort_each(keys, host_offsets, values=None, *, params: Params | None = None, 
                                       _ptr(values_out) if vb else None, vb,
                                       offs.ctypes.data_as(ctypes.POINTER(_i64)), nseg, _ptr(tmp), tmp.numel(),
                                       _pp(params), _stream(keys.device, stream)))
+    _finish("evosort_sort_each", keys.device, tmp, allocated, stream, False)
     return (out, values_out) if vb else out
 
 

@@ -9,6 +9,7 @@ in parallel.  Only the evosort_* C symbols are exported.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import shutil
 import subprocess
@@ -47,10 +48,26 @@ UNITS = [
 ]
 
 
-def _compile(unit, verbose):
+def source_hash() -> str:
+    """First 16 hex digits of SHA-256 over csrc/ and include/ (name order; path, NUL, bytes per file)."""
+    h = hashlib.sha256()
+    files = []
+    for top, rel in ((CSRC, "csrc"), (INCLUDE, "include")):
+        for name in os.listdir(top):
+            path = os.path.join(top, name)
+            if os.path.isfile(path):
+                files.append((f"{rel}/{name}", path))
+    for rel, path in sorted(files):
+        h.update(rel.encode() + b"\0")
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _compile(unit, verbose, defines=()):
     src, obj, extra = unit
     out = os.path.join(BUILD, obj)
-    cmd = [HIPCC] + COMMON + extra + ["-c", os.path.join(CSRC, src), "-o", out]
+    cmd = [HIPCC] + COMMON + list(defines) + extra + ["-c", os.path.join(CSRC, src), "-o", out]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -66,8 +83,9 @@ def _compile(unit, verbose):
 def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(UNITS), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)))
+    defines = [f'-DEVOSORT_SOURCE_HASH="{source_hash()}"']
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda u: _compile(u, verbose), UNITS))
+        objs = list(ex.map(lambda u: _compile(u, verbose, defines), UNITS))
     vscript = os.path.join(BUILD, "exports.map")
     with open(vscript, "w") as f:
         f.write("{ global: evosort_*; local: *; };\n")

@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "capi_internal.hpp"
 #include "evosort.h"
 #include "kernels.hpp"
 #include "merge.hpp"
@@ -21,6 +22,105 @@ using namespace evosort;
 namespace {
 
 thread_local int t_last_hip = 0;
+
+// ------------------------------------------------------ host error words --
+// One host-visible word per device, in pinned host memory that the device
+// maps coherently.  The kernels of a public call store an error bit there on
+// a device-side failure (a look-back wait out of spins, bad segment offsets),
+// besides the error word in the call's scratch.  The host reads it without
+// synchronizing: the next public call on that device finds it nonzero,
+// returns the error instead of running, and clears it.
+struct HostErrorWords {
+    std::mutex mu;
+    std::map<int, uint32_t*> host;    // host address, per device
+    std::map<int, uint32_t*> device;  // the same memory as kernels address it
+};
+HostErrorWords& host_error_words()
+{
+    static HostErrorWords* w = new HostErrorWords();  // never destroyed: outlives static teardown order
+    return *w;
+}
+
+int current_device()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    return dev;
+}
+
+// Kernel address of the current device's word, allocated on first use.  Not
+// allocated while `s` is being captured into a graph (allocation is not
+// allowed there) or when allocation fails: the call then runs without it and
+// its errors are still recorded in its scratch.
+uint32_t* device_error_word(hipStream_t s)
+{
+    const int dev = current_device();
+    if (dev < 0)
+        return nullptr;
+    HostErrorWords& W = host_error_words();
+    std::lock_guard<std::mutex> g(W.mu);
+    auto it = W.device.find(dev);
+    if (it != W.device.end())
+        return it->second;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (cs != hipStreamCaptureStatusNone)
+        return nullptr;
+    void* h = nullptr;
+    void* d = nullptr;
+    if (hipHostMalloc(&h, 64, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(h);
+        return nullptr;
+    }
+    memset(h, 0, 64);
+    W.host[dev] = reinterpret_cast<uint32_t*>(h);
+    W.device[dev] = reinterpret_cast<uint32_t*>(d);
+    return W.device[dev];
+}
+
+}  // namespace
+
+namespace evosort {
+evosort_status status_of_error_bits(uint32_t bits)
+{
+    if (bits == 0)
+        return EVOSORT_OK;
+    return (bits & kDeviceErrBadSegment) ? EVOSORT_ERR_INVALID_ARG : EVOSORT_ERR_DEVICE_TIMEOUT;
+}
+}  // namespace evosort
+
+namespace {
+
+// Reads and clears the current device's pending error (EVOSORT_OK if none).
+evosort_status take_pending_error()
+{
+    const int dev = current_device();
+    if (dev < 0)
+        return EVOSORT_OK;
+    HostErrorWords& W = host_error_words();
+    uint32_t* h = nullptr;
+    {
+        std::lock_guard<std::mutex> g(W.mu);
+        auto it = W.host.find(dev);
+        if (it == W.host.end())
+            return EVOSORT_OK;
+        h = it->second;
+    }
+    if (__atomic_load_n(h, __ATOMIC_ACQUIRE) == 0)
+        return EVOSORT_OK;
+    return status_of_error_bits(__atomic_exchange_n(h, 0u, __ATOMIC_ACQ_REL));
+}
 
 constexpr uint32_t kDefaultSpinLimit = 1u << 24;
 constexpr uint32_t kDefaultInsertion = 8;
@@ -159,6 +259,7 @@ struct Plan {
     MergePlan mp;
     size_t off_mkeys, off_mkeys2, off_mvals, off_parts;
     size_t total;
+    uint32_t* host_error;  // host-visible error word the kernels also set (null: none)
 };
 
 evosort_status check_params(const evosort_params* p)
@@ -264,7 +365,7 @@ evosort_status make_plan(int op, int dtype, int64_t n, uint32_t value_bytes, con
     size_t off = 0;
     if (path == EVOSORT_PATH_RADIX) {
         const int passes = (8 * kb + P->bits - 1) / P->bits;
-        const int status_bytes = n < kStatus32Limit ? 4 : 8;
+        const int status_bytes = n < kStatus32Limit && !(p.debug_flags & EVOSORT_DEBUG_WIDE_STATUS) ? 4 : 8;
         if (!radix_pass_available(kb, vb, P->bits, P->shape, status_bytes))
             return EVOSORT_ERR_UNSUPPORTED_PARAM;
         const uint64_t tile = (uint64_t)P->shape.threads * P->shape.items;
@@ -330,6 +431,9 @@ evosort_status make_plan(int op, int dtype, int64_t n, uint32_t value_bytes, con
         }
         P->off_parts = off;
         off = align_up(off + merge_partition_bytes(P->mp));
+    } else if (path == EVOSORT_PATH_SMALL) {
+        P->off_err = 0;  // the header only: the kernel clears its error word
+        off = kAlign;
     }
     P->total = off;
     P->info.temp_bytes = off;
@@ -453,6 +557,7 @@ evosort_status run_radix(const Plan& P, const void* keys_in, void* keys_out, con
         a.status = at(temp, P.off_status + (size_t)p * P.status_pass_bytes);
         a.tile_counter = ctr + p;
         a.error_word = err;
+        a.host_error = P.host_error;
         a.flags = 0;
         if (argsort && p == 0)
             a.flags |= RADIX_FLAG_IOTA;
@@ -480,7 +585,7 @@ evosort_status run_radix(const Plan& P, const void* keys_in, void* keys_out, con
 }
 
 evosort_status run_small(const Plan& P, const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
-                         hipStream_t s)
+                         void* temp, hipStream_t s)
 {
     SmallSortArgs a{};
     a.keys_in = keys_in;
@@ -490,6 +595,7 @@ evosort_status run_small(const Plan& P, const void* keys_in, void* keys_out, con
     a.n = P.n;
     a.mode = P.op == EVOSORT_OP_SORT ? SMALL_MODE_KEYS
                                      : (P.op == EVOSORT_OP_SORT_PAIRS ? SMALL_MODE_PAIRS : SMALL_MODE_ARGSORT);
+    a.error_word = reinterpret_cast<uint32_t*>(at(temp, P.off_err));
     EVOSORT_LAUNCH("small_sort", s, launch_small_sort(P.kd, P.vb, a, s));
     return EVOSORT_OK;
 }
@@ -514,6 +620,8 @@ evosort_status run_copy(const Plan& P, const void* keys_in, void* keys_out, cons
 evosort_status run_merge(const Plan& P, const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
                          void* temp, hipStream_t s)
 {
+    // no device-side error can occur here; clear the scratch's error word
+    EVOSORT_LAUNCH("fill_zero", s, launch_fill_zero(temp, kAlign, s));
     MergeBuffers b{};
     b.keys_in = keys_in;
     b.keys_out = keys_out;
@@ -540,14 +648,15 @@ evosort_status run_merge(const Plan& P, const void* keys_in, void* keys_out, con
     return EVOSORT_OK;
 }
 
-evosort_status sort_common(int op, int dtype, const void* keys_in, void* keys_out, const void* vals_in,
-                           void* vals_out, uint32_t vb, int64_t n, void* temp, size_t temp_bytes,
-                           const evosort_params* p, void* stream)
+evosort_status sort_impl(int op, int dtype, const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
+                         uint32_t vb, int64_t n, void* temp, size_t temp_bytes, const evosort_params* p,
+                         hipStream_t s, uint32_t* host_error)
 {
     Plan P;
     evosort_status st = make_plan(op, dtype, n, vb, p, &P);
     if (st != EVOSORT_OK)
         return st;
+    P.host_error = host_error;
     if (n == 0)
         return EVOSORT_OK;
     const size_t kbytes = (size_t)n * P.kd.bytes;
@@ -572,12 +681,14 @@ evosort_status sort_common(int op, int dtype, const void* keys_in, void* keys_ou
     st = check_buffers(bufs, sizes, 5, 0, 1, 2, 3);
     if (st != EVOSORT_OK)
         return st;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     switch (P.info.path) {
     case EVOSORT_PATH_COPY:
+        // n == 1: a temp buffer, if one is given, still gets a clear error word
+        if (temp && temp_bytes >= kAlign && !((uintptr_t)temp & (kAlign - 1)))
+            EVOSORT_LAUNCH("fill_zero", s, launch_fill_zero(temp, kAlign, s));
         return run_copy(P, keys_in, keys_out, vals_in, vals_out, s);
     case EVOSORT_PATH_SMALL:
-        return run_small(P, keys_in, keys_out, vals_in, vals_out, s);
+        return run_small(P, keys_in, keys_out, vals_in, vals_out, temp, s);
     case EVOSORT_PATH_RADIX:
         return run_radix(P, keys_in, keys_out, vals_in, vals_out, temp, s);
     case EVOSORT_PATH_MERGE:
@@ -585,6 +696,20 @@ evosort_status sort_common(int op, int dtype, const void* keys_in, void* keys_ou
     default:
         return EVOSORT_ERR_INVALID_ARG;
     }
+}
+
+// A public sort call: reports a pending device-side error of an earlier call
+// first, then runs with the device's host-visible error word.
+evosort_status sort_common(int op, int dtype, const void* keys_in, void* keys_out, const void* vals_in,
+                           void* vals_out, uint32_t vb, int64_t n, void* temp, size_t temp_bytes,
+                           const evosort_params* p, void* stream)
+{
+    const evosort_status pending = take_pending_error();
+    if (pending != EVOSORT_OK)
+        return pending;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    return sort_impl(op, dtype, keys_in, keys_out, vals_in, vals_out, vb, n, temp, temp_bytes, p, s,
+                     device_error_word(s));
 }
 
 
@@ -733,7 +858,8 @@ bool get_side_stream(SideStream* out)
 }
 
 evosort_status run_segmented(const SegPlan& S, const void* keys_in, void* keys_out, const void* vals_in,
-                             void* vals_out, const int64_t* offsets, void* temp, hipStream_t s)
+                             void* vals_out, const int64_t* offsets, void* temp, hipStream_t s,
+                             uint32_t* host_error)
 {
     auto* ctr = reinterpret_cast<SegCounters*>(at(temp, S.off_ctr));
     auto* err = reinterpret_cast<uint32_t*>(at(temp, 0));
@@ -761,6 +887,7 @@ evosort_status run_segmented(const SegPlan& S, const void* keys_in, void* keys_o
     ca.lists = lists;
     ca.large = large;
     ca.error_word = err;
+    ca.host_error = host_error;
     EVOSORT_LAUNCH("seg_classify", s, launch_seg_classify(ca, s));
 
     // large segments: histograms and bases
@@ -852,6 +979,7 @@ evosort_status run_segmented(const SegPlan& S, const void* keys_in, void* keys_o
             a.status = at(temp, S.off_status + (size_t)p * S.status_pass_bytes);
             a.tile_counter = &ctr->pass_ticket[p];
             a.error_word = err;
+            a.host_error = host_error;
             a.flags = (S.debug_flags & EVOSORT_DEBUG_WITHHOLD_TILE0) ? RADIX_FLAG_WITHHOLD_T0 : 0u;
             a.spin_limit = S.spin_limit;
             a.tiles = 0;
@@ -868,9 +996,9 @@ evosort_status run_segmented(const SegPlan& S, const void* keys_in, void* keys_o
     return EVOSORT_OK;
 }
 
-evosort_status segmented_common(int dtype, const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
-                                uint32_t vb, int64_t n, const int64_t* offsets, int64_t nseg, void* temp,
-                                size_t temp_bytes, const evosort_params* p, void* stream)
+evosort_status segmented_impl(int dtype, const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
+                              uint32_t vb, int64_t n, const int64_t* offsets, int64_t nseg, void* temp,
+                              size_t temp_bytes, const evosort_params* p, hipStream_t s, uint32_t* host_error)
 {
     SegPlan S;
     evosort_status st = make_seg_plan(dtype, n, nseg, vb, p, &S);
@@ -891,10 +1019,38 @@ evosort_status segmented_common(int dtype, const void* keys_in, void* keys_out, 
     st = check_buffers(bufs, sizes, 6, 0, 1, 2, 3);
     if (st != EVOSORT_OK)
         return st;
-    return run_segmented(S, keys_in, keys_out, vals_in, vals_out, offsets, temp,
-                         reinterpret_cast<hipStream_t>(stream));
+    return run_segmented(S, keys_in, keys_out, vals_in, vals_out, offsets, temp, s, host_error);
+}
+
+evosort_status segmented_common(int dtype, const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
+                                uint32_t vb, int64_t n, const int64_t* offsets, int64_t nseg, void* temp,
+                                size_t temp_bytes, const evosort_params* p, void* stream)
+{
+    const evosort_status pending = take_pending_error();
+    if (pending != EVOSORT_OK)
+        return pending;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    return segmented_impl(dtype, keys_in, keys_out, vals_in, vals_out, vb, n, offsets, nseg, temp, temp_bytes, p, s,
+                          device_error_word(s));
 }
 }  // namespace
+
+namespace evosort {
+evosort_status server_sort(int dtype, const void* keys_in, void* keys_out, int64_t n, void* temp,
+                           size_t temp_bytes, const evosort_params* p, hipStream_t s, uint32_t* host_error)
+{
+    return sort_impl(EVOSORT_OP_SORT, dtype, keys_in, keys_out, nullptr, nullptr, 0, n, temp, temp_bytes, p, s,
+                     host_error);
+}
+
+evosort_status server_segmented_sort(int dtype, const void* keys_in, void* keys_out, int64_t n,
+                                     const int64_t* offsets, int64_t nseg, void* temp, size_t temp_bytes,
+                                     const evosort_params* p, hipStream_t s, uint32_t* host_error)
+{
+    return segmented_impl(dtype, keys_in, keys_out, nullptr, nullptr, 0, n, offsets, nseg, temp, temp_bytes, p, s,
+                          host_error);
+}
+}  // namespace evosort
 
 // ===================================================================== ABI ===
 extern "C" {
@@ -997,6 +1153,9 @@ evosort_status evosort_radix_pass(int dtype, const void* keys_in, void* keys_out
                                   const evosort_params* p, void* stream)
 {
     const int op = value_bytes ? EVOSORT_OP_SORT_PAIRS : EVOSORT_OP_SORT;
+    const evosort_status pending = take_pending_error();
+    if (pending != EVOSORT_OK)
+        return pending;
     Plan P;
     evosort_status st = make_plan(op, dtype, n, value_bytes, p, &P, FORCE_RADIX);
     if (st != EVOSORT_OK)
@@ -1036,6 +1195,7 @@ evosort_status evosort_radix_pass(int dtype, const void* keys_in, void* keys_out
     a.status = at(temp, P.off_status);
     a.tile_counter = reinterpret_cast<uint32_t*>(at(temp, P.off_ctr));
     a.error_word = reinterpret_cast<uint32_t*>(at(temp, P.off_err));
+    a.host_error = device_error_word(s);
     a.flags = (P.debug_flags & EVOSORT_DEBUG_WITHHOLD_TILE0) ? RADIX_FLAG_WITHHOLD_T0 : 0u;
     a.spin_limit = P.spin_limit;
     a.tiles = (uint32_t)P.info.tiles;
@@ -1253,6 +1413,11 @@ const char* evosort_status_string(int status)
 
 int evosort_last_hip_error(void) { return t_last_hip; }
 
+#ifndef EVOSORT_SOURCE_HASH
+#error "the build passes -DEVOSORT_SOURCE_HASH=<hash of the sources>"
+#endif
+const char* evosort_build_id(void) { return EVOSORT_SOURCE_HASH; }
+
 evosort_status evosort_check_device_error(const void* temp, size_t temp_bytes, void* stream)
 {
     // Every radix, mergesort and segmented scratch layout starts with the
@@ -1267,9 +1432,9 @@ evosort_status evosort_check_device_error(const void* temp, size_t temp_bytes, v
     e = hipMemcpy(&word, temp, 4, hipMemcpyDeviceToHost);
     if (e != hipSuccess)
         return hip_fail(e);
-    if (word & kDeviceErrBadSegment)
-        return EVOSORT_ERR_INVALID_ARG;
-    return word ? EVOSORT_ERR_DEVICE_TIMEOUT : EVOSORT_OK;
+    if (word != 0)
+        (void)take_pending_error();  // this failure is now reported; the next call need not repeat it
+    return status_of_error_bits(word);
 }
 
 void evosort_profile_enable(int on)

@@ -181,6 +181,16 @@ __device__ __forceinline__ void store_agent(T* p, T v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Marks a device-side error in a host-visible word (pinned host memory that
+// the host polls without synchronizing).  A plain system-scope store of the
+// error bit: no atomic crosses to host memory, and every writer stores a
+// nonzero value, so any failure leaves the word nonzero.
+__device__ __forceinline__ void report_host_error(uint32_t* host_error, uint32_t bit)
+{
+    if (host_error)
+        __hip_atomic_store(host_error, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Exclusive scan of one uint32 per thread across a workgroup of THREADS
 // threads.  `wave_tot` must hold THREADS/64 words of LDS.  Returns the
 // exclusive prefix and writes the workgroup total to *total.  Contains one

@@ -50,7 +50,8 @@ struct RadixPassArgs {
     const uint64_t* bases;   // 2^bits first output slots of each digit
     void* status;            // tiles * 2^bits look-back words (zeroed)
     uint32_t* tile_counter;  // zeroed
-    uint32_t* error_word;
+    uint32_t* error_word;    // device error word in the scratch header
+    uint32_t* host_error;    // host-visible word also set on a device-side error (may be null)
     uint32_t flags;          // RADIX_FLAG_*
     uint32_t spin_limit;
     uint32_t tiles;          // workgroups launched (= tiles of the pass)
@@ -81,7 +82,7 @@ hipError_t launch_radix_pass(const KeyDesc& kd, int val_bytes, int bits, RadixSh
 // Zero `bytes` bytes at p (16-byte stores when p and bytes allow).
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
-// Copy `bytes` bytes (device to device) with a kernel.
+// Copy `bytes` bytes device to device (a runtime copy on stream s).
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 }  // namespace evosort

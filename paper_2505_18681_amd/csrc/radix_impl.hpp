@@ -392,13 +392,14 @@ constexpr int kLookBackWindow = 4;
 // Sum of digit b's counts over tiles [0, tile): walk back from tile - 1,
 // reading kLookBackWindow words per round trip, adding aggregates until an
 // inclusive word ends the walk.  An unpublished word is polled (bounded by
-// spin_limit; running out sets *error_word and returns what was summed).
+// spin_limit; running out sets *error_word, and *host_error when given, and
+// returns what was summed).
 // Tile 0 always publishes an inclusive word, so the walk never passes it;
 // window slots before tile 0 re-read tile 0's word (in bounds, never used
 // past it).
 template <typename ST, int BINS>
 __device__ __forceinline__ uint64_t look_back(const ST* status, uint32_t tile, int b, uint32_t spin_limit,
-                                              uint32_t* error_word)
+                                              uint32_t* error_word, uint32_t* host_error)
 {
     constexpr int W = kLookBackWindow;
     uint64_t excl = 0;
@@ -438,6 +439,7 @@ __device__ __forceinline__ uint64_t look_back(const ST* status, uint32_t tile, i
         while (((x = load_agent(&status[(size_t)(uint32_t)t * BINS + b])) >> Status<ST>::kShift) == 0) {
             if (++spins > spin_limit) {
                 atomicOr(error_word, kDeviceErrTimeout);
+                report_host_error(host_error, kDeviceErrTimeout);
                 return excl;
             }
             __builtin_amdgcn_s_sleep(1);
@@ -475,7 +477,7 @@ struct PassLds {
     __attribute__((aligned(16))) unsigned char uni[UNION_BYTES];
     int64_t gofs[BINS];  // output slot of tile position 0, per digit (32-bit values while n < 2^30)
     uint32_t wtot[WAVES];
-    uint32_t next[2];  // tickets, double-buffered by loop parity
+    uint32_t ticket;  // the workgroup's tile number, shared from the lane that took it
 };
 
 // Everything a workgroup does for one tile after it has its tile number.
@@ -715,7 +717,7 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
         if (prefixed) {
             excl = (uint64_t)status[(size_t)tile * BINS + b];  // written before this kernel
         } else if (tile > 0) {
-            excl = look_back<ST, BINS>(status, tile, b, a.spin_limit, a.error_word);
+            excl = look_back<ST, BINS>(status, tile, b, a.spin_limit, a.error_word, a.host_error);
             store_agent(&status[(size_t)tile * BINS + b],
                         (ST)(((ST)kFlagInclusive << Status<ST>::kShift) | (ST)(excl + cnt[j])));
         }
@@ -760,11 +762,10 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
     }
 }
 
-// Persistent: each workgroup loops over tiles taken from the ticket counter.
-// The next ticket is requested while the current tile is processed, so its
-// round trip overlaps useful work.  Tickets are handed out in increasing
-// order to running workgroups, so a tile only ever waits on tiles that are
-// being processed; every workgroup leaves once a ticket is past the last tile.
+// One workgroup per tile.  The tile number is a ticket taken from an atomic
+// counter, not blockIdx: tickets are handed out in the order workgroups start
+// running, so a tile's look-back only ever waits on tiles whose workgroups are
+// already resident, and every wait ends.
 template <int KB, int VB, int BITS, int THREADS, int ITEMS, typename ST>
 __global__ __launch_bounds__(THREADS) void radix_pass_kernel(RadixPassArgs a, OrderMap<typename KeyWord<KB>::U> om)
 {
@@ -775,9 +776,9 @@ __global__ __launch_bounds__(THREADS) void radix_pass_kernel(RadixPassArgs a, Or
     __shared__ Lds L;
 
     if (threadIdx.x == 0)
-        L.next[0] = atomicAdd(a.tile_counter, 1u);
+        L.ticket = atomicAdd(a.tile_counter, 1u);
     __syncthreads();
-    const uint32_t tile = L.next[0];
+    const uint32_t tile = L.ticket;
     if (tile >= a.tiles)
         return;  // uniform across the workgroup
     const int64_t tile_start = (int64_t)tile * TILE;
@@ -809,12 +810,12 @@ __global__ __launch_bounds__(THREADS) void seg_radix_pass_kernel(SegPassArgs sa,
     if (blockIdx.x >= *sa.tile_count)
         return;  // uniform across the workgroup
     if (threadIdx.x == 0)
-        L.next[0] = atomicAdd(sa.base.tile_counter, 1u);
+        L.ticket = atomicAdd(sa.base.tile_counter, 1u);
     __syncthreads();
     // The ticket is the same in every lane; saying so (and the same for the
     // segment's fields) keeps the segment's description and pointers in
     // scalar registers.
-    const uint32_t t = __builtin_amdgcn_readfirstlane(L.next[0]);
+    const uint32_t t = __builtin_amdgcn_readfirstlane(L.ticket);
     const uint32_t slot = __builtin_amdgcn_readfirstlane(sa.tile_slot[t]);
     SegLarge g = sa.large[slot];
     g.begin = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)g.begin >> 32)) << 32) |
@@ -840,37 +841,13 @@ __global__ __launch_bounds__(THREADS) void seg_radix_pass_kernel(SegPassArgs sa,
         pass_tile<false, KB, VB, BITS, THREADS, ITEMS, ST>(a, om, L, lt, tile_start, (uint32_t)left);
 }
 
-// Workgroups resident at once on the current device for a kernel (cached per
-// kernel; the library serves one device at a time per process thread, and
-// all MI355X devices have the same count).
-template <class K>
-int resident_groups(K kernel, int threads, int& cached)
-{
-    if (cached > 0)
-        return cached;
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || cus <= 0 ||
-        per_cu <= 0) {
-        (void)hipGetLastError();
-        return 1024;  // any grid is correct; this only sizes the persistent launch
-    }
-    cached = cus * per_cu;
-    return cached;
-}
-
 template <int KB, int VB, int BITS, int THREADS, int ITEMS, typename ST>
 hipError_t launch_radix_pass_t(const KeyDesc& kd, const RadixPassArgs& a, uint32_t tiles, hipStream_t s)
 {
     using U = typename KeyWord<KB>::U;
     OrderMap<U> om{(U)kd.flip, (U)kd.neg, (U)kd.desc};
-    auto kernel = radix_pass_kernel<KB, VB, BITS, THREADS, ITEMS, ST>;
-    static int cached = 0;  // one per instantiation
-    const uint32_t resident = (uint32_t)resident_groups(kernel, THREADS, cached);
-    const uint32_t grid = tiles;  // one workgroup per tile
-    (void)resident;
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(THREADS), 0, s, a, om);
+    hipLaunchKernelGGL((radix_pass_kernel<KB, VB, BITS, THREADS, ITEMS, ST>), dim3(tiles), dim3(THREADS), 0, s, a,
+                       om);
     return hipGetLastError();
 }
 

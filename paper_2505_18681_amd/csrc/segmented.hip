@@ -62,8 +62,10 @@ __global__ __launch_bounds__(kSegThreads) void seg_validate_kernel(SegClassifyAr
         const int64_t y = a.offsets[i + 1];
         bad = bad || y < x || y - x >= ((int64_t)1 << 30);
     }
-    if (bad)
+    if (bad) {
         atomicOr(a.error_word, kDeviceErrBadSegment);
+        report_host_error(a.host_error, kDeviceErrBadSegment);
+    }
 }
 
 // One thread per segment.

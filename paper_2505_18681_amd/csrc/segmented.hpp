@@ -84,6 +84,7 @@ struct SegClassifyArgs {
     uint32_t* lists;  // (classes + 1) lists of nseg entries
     SegLarge* large;
     uint32_t* error_word;
+    uint32_t* host_error;  // host-visible word also set when the offsets are bad (may be null)
 };
 
 // Per-large-segment kernels walk slots [0, *nlarge) with a grid stride.

@@ -18,6 +18,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "capi_internal.hpp"
 #include "evosort.h"
 
 namespace {
@@ -134,6 +135,14 @@ struct Job {
     int slot = -1;
     int status = EVOSORT_OK;
     int unreleased = 0;
+    std::vector<hipEvent_t> readers;  // copies out of `result` queued on client streams (copy_out)
+};
+
+// Arena ranges of released jobs whose result is still being copied out on a
+// client stream: freed once every one of those copies has finished.
+struct Deferred {
+    Range result;
+    std::vector<hipEvent_t> readers;
 };
 
 struct Slot {
@@ -142,6 +151,8 @@ struct Slot {
     int64_t job = -1;           // running job, or -1
     unsigned char* staging = nullptr;  // pinned host: descriptors and offsets of a batch
     size_t desc_off = 0;        // arena offset of the device copy of the staging area
+    uint32_t* err_host = nullptr;  // pinned, device-mapped word the slot's kernels set on a device error
+    uint32_t* err_dev = nullptr;   // the same word as kernels address it
 };
 
 }  // namespace
@@ -167,6 +178,8 @@ struct evosort_server {
     std::deque<uint64_t> waiting;
     std::unordered_map<uint64_t, Request> reqs;
     std::unordered_map<int64_t, Job> jobs;
+    std::vector<Deferred> deferred;
+    std::vector<hipEvent_t> event_pool;
     evosort_server_stats st{};
     uint32_t running = 0;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -221,6 +234,64 @@ struct evosort_server {
         cv_done.notify_all();
     }
 
+    hipEvent_t get_event()
+    {
+        if (!event_pool.empty()) {
+            hipEvent_t e = event_pool.back();
+            event_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return e;
+    }
+
+    // Frees a released job's result now, or once the copies out of it that
+    // clients queued have finished.
+    void free_result(Job& j)
+    {
+        if (!j.result.bytes)
+            return;
+        if (j.readers.empty()) {
+            arena.release(j.result.off, j.result.bytes);
+        } else {
+            deferred.push_back(Deferred{j.result, std::move(j.readers)});
+            j.readers.clear();
+        }
+        j.result = Range{};
+    }
+
+    // Frees the deferred ranges whose copies have all finished (wait: block
+    // until they have).
+    void reap_deferred(bool wait)
+    {
+        for (size_t i = 0; i < deferred.size();) {
+            Deferred& d = deferred[i];
+            bool done = true;
+            for (hipEvent_t e : d.readers) {
+                const hipError_t q = wait ? hipEventSynchronize(e) : hipEventQuery(e);
+                if (q == hipErrorNotReady) {
+                    done = false;
+                    break;
+                }
+                (void)hipGetLastError();  // a failed copy frees its range all the same
+            }
+            if (!done) {
+                ++i;
+                continue;
+            }
+            for (hipEvent_t e : d.readers)
+                event_pool.push_back(e);
+            arena.release(d.result.off, d.result.bytes);
+            deferred[i] = std::move(deferred.back());
+            deferred.pop_back();
+        }
+        note_bytes();
+    }
+
     // Arena offsets count from the end of the slots' descriptor areas.
     void* ptr(const Range& r) const { return arena_base + (size_t)cfg.streams * staging_bytes + r.off; }
 
@@ -264,7 +335,9 @@ struct evosort_server {
             if (running > st.max_concurrent_jobs)
                 st.max_concurrent_jobs = running;
             note_bytes();
-            int rc = evosort_sort(h.dtype, h.in, h.out, h.n, ptr(rt), rt.bytes, &cfg.params, sl.stream);
+            __atomic_store_n(sl.err_host, 0u, __ATOMIC_RELEASE);  // the slot is idle: no kernel writes it now
+            int rc = evosort::server_sort(h.dtype, h.in, h.out, h.n, ptr(rt), rt.bytes, &cfg.params, sl.stream,
+                                          sl.err_dev);
             if (rc == EVOSORT_OK && hipEventRecord(sl.done, sl.stream) != hipSuccess)
                 rc = EVOSORT_ERR_HIP;
             if (rc != EVOSORT_OK)
@@ -350,6 +423,7 @@ struct evosort_server {
         unsigned char* desc = arena_base + sl.desc_off;
         const size_t desc_bytes = (size_t)nseg * sizeof(GatherItem) + (size_t)(nseg + 1) * sizeof(int64_t);
         int rc = EVOSORT_OK;
+        __atomic_store_n(sl.err_host, 0u, __ATOMIC_RELEASE);
         if (hipMemcpyAsync(desc, sl.staging, desc_bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
             rc = EVOSORT_ERR_HIP;
         if (rc == EVOSORT_OK && total > 0) {
@@ -360,9 +434,10 @@ struct evosort_server {
                 rc = EVOSORT_ERR_HIP;
         }
         if (rc == EVOSORT_OK)
-            rc = evosort_segmented_sort(h.dtype, buf, buf, (int64_t)total,
-                                        reinterpret_cast<const int64_t*>(desc + (size_t)nseg * sizeof(GatherItem)),
-                                        nseg, ptr(rt), rt.bytes, &batch_params, sl.stream);
+            rc = evosort::server_segmented_sort(
+                h.dtype, buf, buf, (int64_t)total,
+                reinterpret_cast<const int64_t*>(desc + (size_t)nseg * sizeof(GatherItem)), nseg, ptr(rt), rt.bytes,
+                &batch_params, sl.stream, sl.err_dev);
         if (rc == EVOSORT_OK && hipEventRecord(sl.done, sl.stream) != hipSuccess)
             rc = EVOSORT_ERR_HIP;
         if (rc != EVOSORT_OK)
@@ -380,11 +455,16 @@ struct evosort_server {
                 if (slots[s].job < 0)
                     continue;
                 const hipError_t q = hipEventQuery(slots[s].done);
-                if (q == hipSuccess)
-                    finish_job(slots[s].job, EVOSORT_OK);
-                else if (q != hipErrorNotReady)
+                if (q == hipSuccess) {
+                    // a device-side failure (a look-back wait out of spins) fails the job
+                    const uint32_t bits = __atomic_load_n(slots[s].err_host, __ATOMIC_ACQUIRE);
+                    finish_job(slots[s].job, evosort::status_of_error_bits(bits));
+                } else if (q != hipErrorNotReady) {
                     finish_job(slots[s].job, EVOSORT_ERR_HIP);
+                }
             }
+            if (!deferred.empty())
+                reap_deferred(false);
             // admit in arrival order while a slot is free and the head fits
             if (!stop) {
                 for (size_t s = 0; s < slots.size() && !waiting.empty(); ++s) {
@@ -397,7 +477,7 @@ struct evosort_server {
             st.waiting = (uint32_t)waiting.size();
             if (stop && running == 0)
                 break;
-            if (running > 0) {
+            if (running > 0 || !deferred.empty()) {
                 lk.unlock();
                 std::this_thread::sleep_for(std::chrono::microseconds(5));
                 lk.lock();
@@ -475,7 +555,12 @@ evosort_status evosort_server_create(const evosort_server_config* cfg, evosort_s
         ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
              hipHostMalloc(reinterpret_cast<void**>(&sl.staging), S->staging_bytes, hipHostMallocDefault) ==
-                 hipSuccess;
+                 hipSuccess &&
+             hipHostMalloc(reinterpret_cast<void**>(&sl.err_host), 64, hipHostMallocMapped | hipHostMallocCoherent) ==
+                 hipSuccess &&
+             hipHostGetDevicePointer(reinterpret_cast<void**>(&sl.err_dev), sl.err_host, 0) == hipSuccess;
+        if (sl.err_host)
+            *sl.err_host = 0;
     }
     if (!ok) {
         (void)hipGetLastError();
@@ -486,6 +571,8 @@ evosort_status evosort_server_create(const evosort_server_config* cfg, evosort_s
                 (void)hipEventDestroy(sl.done);
             if (sl.staging)
                 (void)hipHostFree(sl.staging);
+            if (sl.err_host)
+                (void)hipHostFree(sl.err_host);
         }
         (void)hipFree(base);
         delete S;
@@ -511,7 +598,17 @@ evosort_status evosort_server_destroy(evosort_server* S)
         (void)hipStreamDestroy(sl.stream);
         (void)hipEventDestroy(sl.done);
         (void)hipHostFree(sl.staging);
+        (void)hipHostFree(sl.err_host);
     }
+    // copies out of the arena that clients queued must end before it is freed
+    S->reap_deferred(true);
+    for (auto& kv : S->jobs)
+        for (hipEvent_t e : kv.second.readers) {
+            (void)hipEventSynchronize(e);
+            S->event_pool.push_back(e);
+        }
+    for (hipEvent_t e : S->event_pool)
+        (void)hipEventDestroy(e);
     (void)hipFree(S->arena_base);
     delete S;
     return EVOSORT_OK;
@@ -592,27 +689,36 @@ evosort_status evosort_server_copy_out(evosort_server* S, uint64_t id, void* dst
 {
     if (!S)
         return EVOSORT_ERR_INVALID_ARG;
-    const void* src = nullptr;
-    int64_t n = 0;
-    int kb = 0;
-    {
-        std::lock_guard<std::mutex> g(S->mu);
-        auto it = S->reqs.find(id);
-        if (it == S->reqs.end())
-            return EVOSORT_ERR_INVALID_ARG;
-        if (it->second.status != EVOSORT_OK)
-            return (evosort_status)it->second.status;
-        src = it->second.out;
-        n = it->second.n;
-        kb = key_bytes_of(it->second.dtype);
-    }
-    if (n == 0)
+    // The copy is queued on the client's stream; an event recorded after it
+    // keeps the request's arena range from being reused (after a release)
+    // until the copy has run.
+    hipStream_t cs = reinterpret_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->reqs.find(id);
+    if (it == S->reqs.end())
+        return EVOSORT_ERR_INVALID_ARG;
+    const Request& q = it->second;
+    if (q.status != EVOSORT_OK)
+        return (evosort_status)q.status;
+    if (q.n == 0)
         return EVOSORT_OK;
     if (!dst)
         return EVOSORT_ERR_INVALID_ARG;
-    if (hipMemcpyAsync(dst, src, (size_t)n * kb, hipMemcpyDeviceToDevice, reinterpret_cast<hipStream_t>(stream)) !=
-        hipSuccess)
+    auto jt = S->jobs.find(q.job);
+    if (jt == S->jobs.end())
+        return EVOSORT_ERR_INVALID_ARG;
+    hipEvent_t e = S->get_event();
+    if (!e)
         return EVOSORT_ERR_HIP;
+    if (hipMemcpyAsync(dst, q.out, (size_t)q.n * key_bytes_of(q.dtype), hipMemcpyDeviceToDevice, cs) != hipSuccess ||
+        hipEventRecord(e, cs) != hipSuccess) {
+        (void)hipGetLastError();
+        // the copy may be queued; wait for the stream rather than lose track of it
+        (void)hipStreamSynchronize(cs);
+        S->event_pool.push_back(e);
+        return EVOSORT_ERR_HIP;
+    }
+    jt->second.readers.push_back(e);
     return EVOSORT_OK;
 }
 
@@ -656,12 +762,11 @@ evosort_status evosort_server_release(evosort_server* S, uint64_t id)
                 for (uint64_t r : j.reqs)
                     j.unreleased += S->reqs.count(r) ? 1 : 0;
                 if (j.unreleased == 0) {
-                    if (j.result.bytes)
-                        S->arena.release(j.result.off, j.result.bytes);
+                    S->free_result(j);
                     if (j.scratch.bytes)
                         S->arena.release(j.scratch.off, j.scratch.bytes);
                     S->jobs.erase(jt);
-                    S->note_bytes();
+                    S->reap_deferred(false);  // copies that already ran free their ranges now
                 }
             }
         }
@@ -691,6 +796,7 @@ evosort_status evosort_server_get_stats(evosort_server* S, evosort_server_stats*
     if (!S || !out)
         return EVOSORT_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> g(S->mu);
+    S->reap_deferred(false);
     *out = S->st;
     out->bytes_in_use = S->arena.used();
     out->waiting = (uint32_t)S->waiting.size();

@@ -40,6 +40,8 @@ __global__ __launch_bounds__(THREADS) void small_sort_kernel(SmallSortArgs a, Or
     constexpr bool SPLIT = split_staging<KB, VB, THREADS, ITEMS>();
     __shared__ BlockLsdLds<KB, VB, THREADS, ITEMS, SPLIT> L;
     const bool argsort = a.mode == SMALL_MODE_ARGSORT;
+    if (a.error_word && threadIdx.x == 0)
+        *a.error_word = 0;
     const BlockLsdIo io{a.keys_in, a.keys_out, a.vals_in, a.vals_out, argsort, argsort};
     block_lsd_sort<KB, VB, THREADS, ITEMS, SPLIT>(io, om, L, 0, (uint32_t)a.n);
 }

@@ -22,6 +22,7 @@ struct SmallSortArgs {
     void* vals_out;       // values (pairs) or indices (argsort)
     int64_t n;
     int mode;
+    uint32_t* error_word;  // cleared by the kernel (no device-side error can occur here); may be null
 };
 
 int64_t small_sort_capacity(int key_bytes, int val_bytes);

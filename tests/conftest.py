@@ -9,8 +9,16 @@ if ROOT not in sys.path:
 
 
 # Mutation tests re-run the oracle pins against a deliberately broken copy of
-# the oracle built in a temporary directory; they point the oracle package at
-# that copy through this variable.  Nothing outside the tests sets it.
+# the oracle in a temporary directory: a mutated C library
+# (EVOSORT_TEST_ORACLE_MUTANT, the path of the .so) or a mutated copy of the
+# whole package (EVOSORT_TEST_ORACLE_PKG, the directory holding it).  Nothing
+# outside the tests sets either.
+_MUTANT_PKG = os.environ.get("EVOSORT_TEST_ORACLE_PKG")
+if _MUTANT_PKG:
+    sys.path.insert(0, _MUTANT_PKG)
+    import oracle as _oracle_pkg
+
+    assert os.path.dirname(os.path.dirname(os.path.abspath(_oracle_pkg.__file__))) == os.path.abspath(_MUTANT_PKG)
 _MUTANT = os.environ.get("EVOSORT_TEST_ORACLE_MUTANT")
 if _MUTANT:
     import oracle as _oracle

@@ -43,6 +43,18 @@ def test_every_declared_symbol_is_exported():
         assert hasattr(lib, nm)
 
 
+def test_loaded_library_is_built_from_this_tree():
+    """The library reports the hash of the sources it was compiled from; it must be the tree's current one."""
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location("_evosort_build_script",
+                                                  os.path.join(ROOT, "paper_2505_18681_amd", "build.py"))
+    build = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(build)
+    assert re.fullmatch(r"[0-9a-f]{16}", es.build_id())
+    assert es.build_id() == build.source_hash(), "libevosort.so is stale: rebuild it"
+
+
 def test_only_abi_symbols_are_exported():
     out = subprocess.run(["nm", "-D", "--defined-only", es.LIB_PATH], capture_output=True, text=True,
                          check=True).stdout

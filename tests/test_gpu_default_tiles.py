@@ -1,0 +1,87 @@
+"""Every default tile shape of the radix passes for large arrays, element by element against the oracle.
+
+Above 2^21 keys the library takes its large-array tile per (key bytes, value
+bytes): 768 x 24 for 4-byte keys alone or with 4-byte values, 512 x 24 for
+4-byte keys with 8-byte values and for 8-byte keys with 4-byte values,
+768 x 12 for 8-byte keys alone (the kernel of the 1e9 int64 benchmark sort),
+512 x 16 for 8-byte keys with 8-byte values (Sec. 4, Algorithms 4 and 5: one
+stable pass per digit).  Each shape runs with 32-bit look-back words (every
+n < 2^30) and with 64-bit ones (every n >= 2^30, reached here at a small size
+through EVOSORT_DEBUG_WIDE_STATUS), for keys only, key-value pairs with 4- and
+8-byte values and argsort with int32 and int64 indices, at a size that spans
+hundreds of tiles and ends in a ragged tile.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import assert_bits_equal, require_gpu, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+N = (1 << 22) + 12345
+EXPECTED_TILE = {(4, 0): (768, 24), (4, 4): (768, 24), (4, 8): (512, 24),
+                 (8, 0): (768, 12), (8, 4): (512, 24), (8, 8): (512, 16)}
+_CACHE = {}
+
+
+def _case(dt):
+    """Keys with ties (every 5th key repeats one value, a run of equal keys) and, for floats, the edge mix;
+    the oracle's stable permutation of them."""
+    if dt not in _CACHE:
+        if np.dtype(dt).kind == "f":
+            keys = workloads.float_mix(dt, N, 31)
+        else:
+            keys = workloads.uniform(dt, N, 31)
+        keys[::5] = keys[7]
+        keys[1000:5000] = keys[3]
+        _CACHE.clear()
+        _CACHE[dt] = (keys, oracle.stable_perm(keys))
+    return _CACHE[dt]
+
+
+@pytest.mark.parametrize("wide", [False, True], ids=["status32", "status64"])
+@pytest.mark.parametrize("dt", [np.int32, np.float32, np.uint32, np.int64, np.float64])
+def test_default_large_array_tiles(dt, wide):
+    import torch
+
+    es = require_gpu()
+    keys, perm = _case(dt)
+    kb = np.dtype(dt).itemsize
+    code = es.dtype_code(torch.from_numpy(keys[:1]).dtype)
+    p = es.default_params(debug_flags=es.DEBUG_WIDE_STATUS if wide else 0)
+    for op, vb in ((es.OP_SORT, 0), (es.OP_SORT_PAIRS, 4), (es.OP_SORT_PAIRS, 8), (es.OP_ARGSORT, 4),
+                   (es.OP_ARGSORT, 8)):
+        info = es.plan(op, code, N, vb, p)
+        assert info["path_name"] == "radix"
+        assert (info["block_threads"], info["items_per_thread"]) == EXPECTED_TILE[(kb, vb)], (op, vb, info)
+        assert info["status_bytes"] == (8 if wide else 4)
+        assert info["tiles"] > 200
+    want = keys[perm]
+    k = to_dev(keys)
+    assert_bits_equal(to_np(es.sort(k, params=p, check=True)), want, "keys")
+    v4 = (np.arange(N, dtype=np.int64) * 7 + 3).astype(np.int32)
+    k4, o4 = es.sort_pairs(k, to_dev(v4), params=p, check=True)
+    assert_bits_equal(to_np(k4), want, "pairs(4) keys")
+    assert_bits_equal(to_np(o4), v4[perm], "pairs(4) values")
+    v8 = (np.arange(N, dtype=np.int64) * 2654435761) % (2 ** 61)
+    k8, o8 = es.sort_pairs(k, to_dev(v8), params=p, check=True)
+    assert_bits_equal(to_np(k8), want, "pairs(8) keys")
+    assert_bits_equal(to_np(o8), v8[perm], "pairs(8) values")
+    assert np.array_equal(to_np(es.argsort(k, index_dtype=torch.int32, params=p, check=True)),
+                          perm.astype(np.int32)), "argsort int32"
+    assert np.array_equal(to_np(es.argsort(k, index_dtype=torch.int64, params=p, check=True)), perm), \
+        "argsort int64"
+
+
+@pytest.mark.parametrize("wide", [False, True], ids=["status32", "status64"])
+def test_default_tiles_descending_and_in_place(wide):
+    """The 8-byte default tile with descending order, sorted in place (odd pass counts need no copy here:
+    8 passes)."""
+    es = require_gpu()
+    keys, _ = _case(np.int64)
+    p = es.default_params(descending=1, debug_flags=es.DEBUG_WIDE_STATUS if wide else 0)
+    k = to_dev(keys)
+    es.sort(k, params=p, out=k, check=True)
+    assert_bits_equal(to_np(k), oracle.sort(keys, descending=True), "descending in place")

@@ -5,8 +5,10 @@ result is checked by (1) outputs the oracle computes one by one -- the rank of
 sampled input elements under the stable sort -- and (2) properties that
 together equal "is the stable sort":
 
-* keys-only: ordered, and the same multiset (the argsort of the same input is
-  a permutation and gathers exactly the sorted keys);
+* keys-only: ordered, and the same multiset -- the argsort of the same input
+  is a permutation and gathers exactly the sorted keys, or (1e10 keys) a count
+  table over all 2^32 values, +1 for every input key and -1 for every output
+  key, is zero everywhere;
 * argsort / key-value with the original index as value: the indices form a
   permutation, gathering the input by them gives the sorted keys bit for bit,
   and (order key, index) is strictly increasing (stability).
@@ -15,6 +17,8 @@ Property checks run on the host with numpy over the copied-back arrays, or on
 the GPU with plain torch operations (never with this library).  Workloads:
 
 * 1e9 uniform int32 keys, default parameters (the benchmark's sort);
+* 1e9 uniform int64 keys, default parameters (the benchmark's int64 sort),
+  keys only and argsort;
 * 1e8 int32 keys for each of the eight distributions of the sweep;
 * 2^30 - 1 and 2^30 int32 keys, either side of the switch from 32-bit to
   64-bit look-back words;
@@ -86,6 +90,31 @@ def test_benchmark_sort_1e9_int32():
     _progress("1e9 int32: oracle samples")
     _check_ranks(keys, out, 6, 1)
     _progress("1e9 int32: exact properties")
+    _check_argsort_exact(keys, out, idx)
+
+
+@pytest.mark.timeout(900)
+def test_benchmark_sort_1e9_int64():
+    """The 1e9 int64 sort the benchmark times (768 x 12 tiles, eight passes), keys only and argsort with
+    int32 indices (512 x 24 tiles of 8-byte keys and 4-byte values)."""
+    es = require_gpu()
+    import torch
+
+    n = 1_000_000_000
+    _progress("1e9 int64: generating")
+    keys = workloads.uniform(np.int64, n, workloads.DEFAULT_SEED + 1)
+    keys[: n // 4] = keys[n // 4: n // 2]  # a quarter of the keys appear twice: ties
+    d_keys = to_dev(keys)
+    info = es.plan(es.OP_SORT, es.INT64, n)
+    assert info["path_name"] == "radix" and (info["block_threads"], info["items_per_thread"]) == (768, 12)
+    _progress("1e9 int64: sorting")
+    out = to_np(es.sort(d_keys, check=True))
+    idx = to_np(es.argsort(d_keys, index_dtype=torch.int32, check=True)).astype(np.int64)
+    del d_keys
+    torch.cuda.empty_cache()
+    _progress("1e9 int64: oracle samples")
+    _check_ranks(keys, out, 4, 8)
+    _progress("1e9 int64: exact properties")
     _check_argsort_exact(keys, out, idx)
 
 
@@ -181,23 +210,30 @@ def test_1e10_int32_keys():
     info = es.plan(es.OP_SORT, es.INT32, n)
     assert info["path_name"] == "radix" and info["status_bytes"] == 8
     _progress("1e10 int32: sorting")
-    d_out = es.sort(d_keys)
-    torch.cuda.synchronize()
+    d_temp_holder = torch.empty(es.temp_bytes(es.OP_SORT, es.INT32, n), dtype=torch.uint8, device="cuda")
+    d_out = es.sort(d_keys, temp=d_temp_holder, check=True)
+    del d_temp_holder
+    torch.cuda.empty_cache()
     _progress("1e10 int32: properties on the GPU")
     # ordered
     for s in range(0, n - 1, step):
         e = min(s + step + 1, n)
         assert _gpu_sorted_int(d_out[s:e]), f"out of order in [{s}, {e})"
-    # same multiset: counts of every value of the top 16 bits, and of every
-    # value of the low 16 bits, agree (computed with torch.bincount)
-    for shift in (16, 0):
-        h_in = torch.zeros(65536, dtype=torch.int64, device="cuda")
-        h_out = torch.zeros_like(h_in)
+    # same multiset, exactly: one int32 counter per 32-bit value (16 GiB), +1 for every input key and -1
+    # for every output key; all counters must end at zero.  Together with the order this is equality with
+    # the sorted input, which is unique for keys only.
+    counts = torch.zeros(1 << 32, dtype=torch.int32, device="cuda")
+    for src, sign in ((d_keys, 1), (d_out, -1)):
+        delta = torch.full((step,), sign, dtype=torch.int32, device="cuda")
         for s in range(0, n, step):
-            for src, h in ((d_keys, h_in), (d_out, h_out)):
-                v = (src[s:s + step].to(torch.int64) + 2**31) >> shift & 0xFFFF
-                h += torch.bincount(v, minlength=65536)
-        assert torch.equal(h_in, h_out), f"multiset differs (bits {shift}..{shift + 15})"
+            chunk = src[s:s + step]
+            slot = chunk.to(torch.int64) + 2**31  # the key's offset-binary value, 0 .. 2^32 - 1
+            counts.index_add_(0, slot, delta[:chunk.numel()])
+            del slot
+        del delta
+    assert not bool(counts.any().item()), "the output is not a permutation of the input"
+    del counts
+    torch.cuda.empty_cache()
     _progress("1e10 int32: oracle samples")
     out_host = np.empty(n, dtype=np.int32)
     for s in range(0, n, step):

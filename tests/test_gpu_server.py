@@ -1,5 +1,7 @@
-"""Sort server on the GPU: every result of a mixed, overlapping, batched request stream is the same as
-the request sorted alone (bit for bit; the stable sort is unique), and the HBM budget holds."""
+"""Sort server on the GPU: every result of a mixed, overlapping, batched request stream equals the oracle's
+stable sort of that request and the same request sorted alone (bit for bit; the stable sort is unique),
+the HBM budget holds, results copied out and released without a synchronization stay intact, and a job
+whose kernels fail is reported as failed."""
 import time
 
 import numpy as np
@@ -43,10 +45,10 @@ def test_mixed_stream_matches_each_request_alone():
                 time.sleep(0.0005)  # arrivals while earlier work runs
         for i, (rid, keys, d) in enumerate(zip(ids, reqs, dev)):
             got = to_np(srv.result(rid))
+            assert_bits_equal(got, keys[oracle.stable_perm(keys)], f"request {i} (n={keys.size}, {keys.dtype}) "
+                                                                   "vs oracle")
             alone = to_np(es.sort(d))
-            assert_bits_equal(got, alone, f"request {i} (n={keys.size}, {keys.dtype}) vs alone")
-            if i % 10 == 0:
-                assert_bits_equal(got, keys[oracle.stable_perm(keys)], f"request {i} vs oracle")
+            assert_bits_equal(got, alone, f"request {i} vs alone")
             srv.release(rid)
         st = srv.stats()
     assert st["completed"] == st["submitted"] == len(reqs) and st["failed"] == 0
@@ -66,7 +68,7 @@ def test_budget_bounds_the_arena_and_every_request_finishes():
         ids = [srv.submit(d) for d in dev]
         for rid, keys in zip(ids, reqs):
             got = to_np(srv.result(rid))
-            assert_bits_equal(got, np.sort(keys, kind="stable"), "budgeted request")
+            assert_bits_equal(got, oracle.sort(keys), "budgeted request")
             srv.release(rid)
         st = srv.stats()
     assert st["peak_bytes"] <= budget and st["completed"] == len(reqs)
@@ -82,7 +84,7 @@ def test_over_budget_request_is_refused():
         assert e.value.status == es.ERR_OVER_BUDGET
         small = workloads.uniform(np.int64, 1000, 6)
         rid = srv.submit(to_dev(small))
-        assert_bits_equal(to_np(srv.result(rid)), np.sort(small, kind="stable"), "small after refusal")
+        assert_bits_equal(to_np(srv.result(rid)), oracle.sort(small), "small after refusal")
 
 
 def test_unreleased_results_hold_memory_until_release():
@@ -119,3 +121,58 @@ def test_empty_request():
         assert srv.done(rid)
         assert srv.result(rid).numel() == 0
         srv.release(rid)
+
+
+def test_result_then_release_without_synchronizing():
+    """result() queues a copy on the client's stream and release() returns the arena range at once; the
+    range must not be handed to a later job before that copy has run.  New requests are admitted into the
+    freed memory while the copies may still be queued; every copied result is checked against the oracle
+    after one final synchronization."""
+    es = require_gpu()
+    import torch
+
+    reqs = [workloads.uniform(np.int64, int(n), 90 + i)
+            for i, n in enumerate(np.random.default_rng(4).integers(100_000, 900_000, 48))]
+    dev = [to_dev(k) for k in reqs]
+    stream = torch.cuda.current_stream()
+    copies = []
+    # a small budget: few requests fit at once, so admission reuses released ranges right away
+    with es.Server(hbm_budget_bytes=48 << 20, streams=4, batch_max_keys=0) as srv:
+        ids = [srv.submit(d) for d in dev[:8]]
+        nxt = 8
+        while ids:
+            rid = ids.pop(0)
+            srv.wait(rid)
+            # keep the client stream busy so the copy below is still queued when release() runs
+            torch.cuda._sleep(2_000_000)
+            copies.append(srv.result(rid))
+            srv.release(rid)
+            if nxt < len(dev):
+                ids.append(srv.submit(dev[nxt]))
+                nxt += 1
+        stream.synchronize()
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    for i, (got, keys) in enumerate(zip(copies, reqs)):
+        assert_bits_equal(to_np(got), oracle.sort(keys), f"copied result {i}")
+
+
+def test_failed_job_is_reported_not_ok():
+    """A served sort whose look-back wait runs out (a debug switch withholds tile 0's counts) finishes with
+    EVOSORT_ERR_DEVICE_TIMEOUT; the failure stays with the server and the next sorts run normally."""
+    es = require_gpu()
+    bad = es.default_params(fallback_threshold=0, spin_limit=2000, debug_flags=es.DEBUG_WITHHOLD_TILE0)
+    keys = workloads.uniform(np.int32, 60_000, 12)
+    with es.Server(hbm_budget_bytes=64 << 20, streams=2, batch_max_keys=0, params=bad) as srv:
+        rid = srv.submit(to_dev(keys))
+        with pytest.raises(es.EvosortError) as e:
+            srv.wait(rid)
+        assert e.value.status == es.ERR_DEVICE_TIMEOUT
+        assert srv.stats()["failed"] == 1
+        srv.release(rid)
+    # the server's failure is not charged to the library's next public call
+    assert_bits_equal(to_np(es.sort(to_dev(keys), check=True)), oracle.sort(keys), "after a failed job")
+    good = es.default_params(fallback_threshold=0)
+    with es.Server(hbm_budget_bytes=64 << 20, streams=2, batch_max_keys=0, params=good) as srv:
+        rid = srv.submit(to_dev(keys))
+        assert_bits_equal(to_np(srv.result(rid)), oracle.sort(keys), "good server")

@@ -176,20 +176,91 @@ def test_repeat_is_deterministic():
 
 
 def test_lookback_timeout_is_reported_not_hung():
-    """Tile 0 withholds its counts: the bounded look-back wait runs out and is reported."""
+    """Tile 0 withholds its counts: the bounded look-back wait runs out and is reported -- by the next
+    library call once the failing kernel has run, by the check on its scratch, and at once in checked mode.
+    Each failure is reported once; afterwards the library sorts normally."""
     es = require_gpu()
     import torch
 
     keys = workloads.uniform(np.uint32, 50_000, 1)
-    p = es.default_params(fallback_threshold=0, spin_limit=2000, debug_flags=es.DEBUG_WITHHOLD_TILE0)
-    need = es.temp_bytes(es.OP_SORT, es.UINT32, keys.size, 0, p)
+    k = to_dev(keys)
+    bad = es.default_params(fallback_threshold=0, spin_limit=2000, debug_flags=es.DEBUG_WITHHOLD_TILE0)
+    good = es.default_params(fallback_threshold=0)
+    need = es.temp_bytes(es.OP_SORT, es.UINT32, keys.size, 0, bad)
     temp = torch.empty(need, dtype=torch.uint8, device="cuda")
-    es.sort(to_dev(keys), params=p, temp=temp)
-    assert es.check_device_error(temp) == es.ERR_DEVICE_TIMEOUT
-    # the same scratch, used normally afterwards, reports no error and sorts right
-    out = es.sort(to_dev(keys), params=es.default_params(fallback_threshold=0), temp=temp)
+    # 1. the failing call returns (its kernels run later); the next call reports it and enqueues nothing
+    es.sort(k, params=bad, temp=temp)
+    torch.cuda.synchronize()
+    out = torch.zeros_like(k)
+    with pytest.raises(es.EvosortError) as e:
+        es.sort(k, params=good, out=out)
+    assert e.value.status == es.ERR_DEVICE_TIMEOUT
+    torch.cuda.synchronize()
+    assert not bool(out.any().item()), "the reporting call enqueued nothing"
+    assert es.check_device_error(temp) == es.ERR_DEVICE_TIMEOUT  # still recorded in the failed call's scratch
+    # 2. reported once: the next call runs
+    assert_bits_equal(to_np(es.sort(k, params=good)), oracle.sort(keys), "after the report")
+    # 3. checked mode raises from the failing call itself, and the failure is not reported again
+    with pytest.raises(es.EvosortError) as e:
+        es.sort(k, params=bad, temp=temp, check=True)
+    assert e.value.status == es.ERR_DEVICE_TIMEOUT
+    for op in ("pairs", "argsort"):
+        with pytest.raises(es.EvosortError) as e:
+            if op == "pairs":
+                es.sort_pairs(k, k.view(torch.int32), params=bad, check=True)
+            else:
+                es.argsort(k, params=bad, check=True)
+        assert e.value.status == es.ERR_DEVICE_TIMEOUT, op
+    # 4. the same scratch, used normally afterwards, reports no error and sorts right
+    out = es.sort(k, params=good, temp=temp, check=True)
     assert es.check_device_error(temp) == es.OK
     assert_bits_equal(to_np(out), oracle.sort(keys), "after timeout")
+
+
+def test_error_word_is_cleared_by_every_routine():
+    """A scratch buffer whose error word was set by a failed radix call reads clear after a small-array,
+    mergesort or radix call reuses it."""
+    es = require_gpu()
+    import torch
+
+    keys = workloads.uniform(np.int32, 40_000, 2)
+    k = to_dev(keys)
+    bad = es.default_params(fallback_threshold=0, spin_limit=2000, debug_flags=es.DEBUG_WITHHOLD_TILE0)
+    temp = torch.empty(es.temp_bytes(es.OP_SORT, es.INT32, keys.size, 0, bad), dtype=torch.uint8, device="cuda")
+    for path, params, n in (("small", es.default_params(), 3000),
+                            ("merge", es.default_params(algo=es.ALGO_MERGE, fallback_threshold=0), keys.size),
+                            ("radix", es.default_params(fallback_threshold=0), keys.size)):
+        with pytest.raises(es.EvosortError):
+            es.sort(k, params=bad, temp=temp, check=True)
+        assert es.check_device_error(temp) == es.ERR_DEVICE_TIMEOUT
+        assert es.plan(es.OP_SORT, es.INT32, n, 0, params)["path_name"] == path
+        out = es.sort(k[:n], params=params, temp=temp, check=True)
+        assert es.check_device_error(temp) == es.OK, path
+        assert_bits_equal(to_np(out), oracle.sort(keys[:n]), path)
+
+
+def test_call_on_a_side_stream_keeps_its_buffers():
+    """A sort enqueued on another stream than the current one: the scratch and output the binding
+    allocates are held for that stream, so allocations and writes on the current stream right after the
+    call cannot land in them while the sort still runs."""
+    es = require_gpu()
+    import torch
+
+    n = 1 << 24
+    keys = workloads.uniform(np.int32, n, 5)
+    k = to_dev(keys)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    results = []
+    for _ in range(3):
+        results.append(es.sort(k, stream=side))          # binding-allocated scratch, freed on return
+        junk = torch.empty(3 * n, dtype=torch.int32, device="cuda")
+        junk.fill_(-1)                                   # current stream: must not reuse that memory yet
+        del junk
+    side.synchronize()
+    want = oracle.sort(keys)
+    for r in results:
+        assert_bits_equal(to_np(r), want, "side-stream sort")
 
 
 @pytest.mark.parametrize("path", ["small", "radix", "merge"])

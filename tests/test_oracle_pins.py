@@ -306,6 +306,17 @@ def test_aps_branches_match_paper_table(golden):
         assert got == expect, (n, t_np, a_code, is_int)
 
 
+def test_aps_gpu_readings(golden):
+    """The dispatch rule with the GPU library's readings (one-workgroup capacity, A_code 0, float keys),
+    against a table written by hand from those readings."""
+    rows = golden("aps_dispatch_gpu.txt")
+    assert len(rows) >= 20
+    for n, t_np, a_code, is_int, cap, rff, expect in rows:
+        got = oracle.aps_path(int(n), bool(int(is_int)), int(a_code), int(t_np), small_capacity=int(cap),
+                              radix_for_floats=bool(int(rff)))
+        assert got == expect, (n, t_np, a_code, is_int, cap, rff)
+
+
 def test_struct_roundtrip_sanity():
     # the float golden file's hex patterns are the standard encodings
     assert struct.unpack("<f", struct.pack("<I", 0x3FC00000))[0] == 1.5
