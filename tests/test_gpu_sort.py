@@ -196,7 +196,7 @@ def test_lookback_timeout_is_reported_not_hung():
         es.sort(k, params=good, out=out)
     assert e.value.status == es.ERR_DEVICE_TIMEOUT
     torch.cuda.synchronize()
-    assert not bool(out.any().item()), "the reporting call enqueued nothing"
+    assert not bool(out.view(torch.int32).any().item()), "the reporting call enqueued nothing"
     assert es.check_device_error(temp) == es.ERR_DEVICE_TIMEOUT  # still recorded in the failed call's scratch
     # 2. reported once: the next call runs
     assert_bits_equal(to_np(es.sort(k, params=good)), oracle.sort(keys), "after the report")
@@ -207,7 +207,7 @@ def test_lookback_timeout_is_reported_not_hung():
     for op in ("pairs", "argsort"):
         with pytest.raises(es.EvosortError) as e:
             if op == "pairs":
-                es.sort_pairs(k, k.view(torch.int32), params=bad, check=True)
+                es.sort_pairs(k, k.view(torch.int32).clone(), params=bad, check=True)
             else:
                 es.argsort(k, params=bad, check=True)
         assert e.value.status == es.ERR_DEVICE_TIMEOUT, op
