@@ -215,6 +215,29 @@ evosort_status evosort_sort_pairs(int dtype, const void *keys_in, void *keys_out
 evosort_status evosort_argsort(int dtype, const void *keys_in, void *idx_out, uint32_t index_bytes, int64_t n,
                                void *temp, size_t temp_bytes, const evosort_params *p, void *stream);
 
+/*
+ * Allocation-free sort, for callers that cannot allocate device memory or
+ * call allocating routines (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid it).  The same sort as evosort_sort, with its
+ * scratch in a device array inside the library instead of a caller's temp:
+ * EVOSORT_NOALLOC_SCRATCH_BYTES per device, held from the library's load on
+ * that device until the process ends.  The call allocates, creates and frees
+ * nothing (profiling events are not recorded for it).
+ *   - Sizes whose scratch (evosort_plan(EVOSORT_OP_SORT, ...).temp_bytes of
+ *     the routine the call takes) exceeds EVOSORT_NOALLOC_SCRATCH_BYTES return
+ *     EVOSORT_ERR_TEMP_TOO_SMALL and enqueue nothing (about 16e6 4-byte or
+ *     8e6 8-byte keys fit).
+ *   - Every call on a device shares that device's array, which keeps the last
+ *     call's contents; each call clears what must start at zero.  Calls that
+ *     overlap in time on one device (other streams, other host threads) race
+ *     on the array and give undefined results: serialize them.
+ *   - Device-side errors are reported at the next call as for evosort_sort;
+ *     evosort_check_device_error does not apply (there is no temp).
+ */
+#define EVOSORT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+evosort_status evosort_sort_noalloc(int dtype, const void *keys_in, void *keys_out, int64_t n,
+                                    const evosort_params *p, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Single steps of the two routines, exported so each can be checked alone.  */
 /* ------------------------------------------------------------------------ */

@@ -59,6 +59,7 @@ EXPORTED = (
     "evosort_server_default_config", "evosort_server_create", "evosort_server_destroy", "evosort_server_submit",
     "evosort_server_result", "evosort_server_wait", "evosort_server_copy_out", "evosort_server_times",
     "evosort_server_release", "evosort_server_drain", "evosort_server_get_stats", "evosort_build_id",
+    "evosort_sort_noalloc",
 )
 
 
@@ -136,6 +137,8 @@ _lib.evosort_plan.argtypes = [_i32, _i32, _i64, _u32, _P, ctypes.POINTER(PlanInf
 _lib.evosort_sort.argtypes = [_i32, _vp, _vp, _i64, _vp, _sz, _P, _vp]
 _lib.evosort_sort_pairs.argtypes = [_i32, _vp, _vp, _vp, _vp, _u32, _i64, _vp, _sz, _P, _vp]
 _lib.evosort_argsort.argtypes = [_i32, _vp, _vp, _u32, _i64, _vp, _sz, _P, _vp]
+_lib.evosort_sort_noalloc.argtypes = [_i32, _vp, _vp, _i64, _P, _vp]
+_lib.evosort_sort_noalloc.restype = ctypes.c_int
 _lib.evosort_radix_histogram.argtypes = [_i32, _vp, _i64, _u32, _vp, _vp, _vp, _sz, _vp]
 _lib.evosort_radix_pass.argtypes = [_i32, _vp, _vp, _vp, _vp, _u32, _i64, _u32, _vp, _sz, _P, _vp]
 _lib.evosort_merge_block_sort.argtypes = [_i32, _vp, _vp, _vp, _vp, _u32, _i64, _P, ctypes.POINTER(_i64), _vp]
@@ -376,6 +379,31 @@ def argsort(keys, *, index_dtype=None, params: Params | None = None, out=None, s
         _check("evosort_argsort", _lib.evosort_argsort(code, _ptr(keys), _ptr(out), ib, n, _ptr(tmp), tmp.numel(),
                                                        _pp(params), _stream(keys.device, stream)))
     _finish("evosort_argsort", keys.device, tmp, allocated, stream, check)
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # EVOSORT_NOALLOC_SCRATCH_BYTES
+
+
+def sort_noalloc(keys, *, params: Params | None = None, out=None, stream=None):
+    """:func:`sort` through ``evosort_sort_noalloc``: the library takes no scratch from the caller and allocates
+    nothing (its scratch is a device array of ``NOALLOC_SCRATCH_BYTES`` inside the library, shared by every
+    such call on the device, so calls that overlap in time on one device race).  Only ``out``, when not
+    given, is allocated here."""
+    torch = _torch()
+    keys = _key_tensor(keys)
+    code = dtype_code(keys.dtype)
+    allocated = []
+    if out is None:
+        out = torch.empty_like(keys)
+        allocated.append(out)
+    _key_tensor(out, "out")
+    if out.dtype != keys.dtype or out.numel() != keys.numel():
+        raise ValueError("out must match keys in dtype and length")
+    with torch.cuda.device(keys.device):
+        _check("evosort_sort_noalloc", _lib.evosort_sort_noalloc(code, _ptr(keys), _ptr(out), keys.numel(),
+                                                                 _pp(params), _stream(keys.device, stream)))
+    _finish("evosort_sort_noalloc", keys.device, None, allocated, stream, False)
     return out
 
 

@@ -39,6 +39,7 @@ UNITS = [
     ("segmented.hip", "segmented.o", []),
     ("capi.cpp", "capi.o", ["-x", "hip"]),
     ("server.cpp", "server.o", ["-x", "hip"]),
+    ("noalloc.cpp", "noalloc.o", ["-x", "hip"]),
 ] + [
     ("radix_inst.hip", f"radix_k{kb}_v{vb}.o", [f"-DEVOSORT_KB={kb}", f"-DEVOSORT_VB={vb}"])
     for kb in (4, 8) for vb in (0, 4, 8)

@@ -22,6 +22,9 @@ using namespace evosort;
 namespace {
 
 thread_local int t_last_hip = 0;
+// Set while the allocation-free sort runs: its launches are never bracketed
+// by profiling events (creating an event may allocate).
+thread_local bool t_no_events = false;
 
 // ------------------------------------------------------ host error words --
 // One host-visible word per device, in pinned host memory that the device
@@ -101,6 +104,19 @@ evosort_status status_of_error_bits(uint32_t bits)
 }  // namespace evosort
 
 namespace {
+
+// Kernel address of the current device's word if it has been allocated
+// already (never allocates).
+uint32_t* existing_device_error_word()
+{
+    const int dev = current_device();
+    if (dev < 0)
+        return nullptr;
+    HostErrorWords& W = host_error_words();
+    std::lock_guard<std::mutex> g(W.mu);
+    auto it = W.device.find(dev);
+    return it == W.device.end() ? nullptr : it->second;
+}
 
 // Reads and clears the current device's pending error (EVOSORT_OK if none).
 evosort_status take_pending_error()
@@ -204,7 +220,7 @@ hipError_t timed(const char* name, hipStream_t s, F&& launch)
     bool on;
     {
         std::lock_guard<std::mutex> g(P.mu);
-        on = P.on;
+        on = P.on && !t_no_events;
     }
     if (!on)
         return launch();
@@ -471,6 +487,14 @@ evosort_status hip_fail(hipError_t e)
     t_last_hip = (int)e;
     return EVOSORT_ERR_HIP;
 }
+
+}  // namespace
+
+namespace evosort {
+evosort_status record_hip_failure(hipError_t e) { return hip_fail(e); }
+}  // namespace evosort
+
+namespace {
 
 #define EVOSORT_LAUNCH(name, s, expr)                         \
     do {                                                      \
@@ -1041,6 +1065,25 @@ evosort_status server_sort(int dtype, const void* keys_in, void* keys_out, int64
 {
     return sort_impl(EVOSORT_OP_SORT, dtype, keys_in, keys_out, nullptr, nullptr, 0, n, temp, temp_bytes, p, s,
                      host_error);
+}
+
+evosort_status sort_in_scratch(int dtype, const void* keys_in, void* keys_out, int64_t n, const evosort_params* p,
+                               hipStream_t s, void* scratch, size_t scratch_bytes)
+{
+    const evosort_status pending = take_pending_error();
+    if (pending != EVOSORT_OK)
+        return pending;
+    Plan P;
+    const evosort_status st = make_plan(EVOSORT_OP_SORT, dtype, n, 0, p, &P);
+    if (st != EVOSORT_OK)
+        return st;
+    if (P.total > scratch_bytes)
+        return EVOSORT_ERR_TEMP_TOO_SMALL;
+    t_no_events = true;
+    const evosort_status r = sort_impl(EVOSORT_OP_SORT, dtype, keys_in, keys_out, nullptr, nullptr, 0, n, scratch,
+                                       scratch_bytes, p, s, existing_device_error_word());
+    t_no_events = false;
+    return r;
 }
 
 evosort_status server_segmented_sort(int dtype, const void* keys_in, void* keys_out, int64_t n,

@@ -22,4 +22,14 @@ evosort_status server_segmented_sort(int dtype, const void* keys_in, void* keys_
 // Status of a device error word's bits (0: EVOSORT_OK).
 evosort_status status_of_error_bits(uint32_t bits);
 
+// evosort_sort with its scratch at `scratch` (scratch_bytes long): reports an
+// earlier call's pending device error first, returns
+// EVOSORT_ERR_TEMP_TOO_SMALL when the sort needs more scratch, and creates,
+// allocates and frees nothing (no profiling events either).
+evosort_status sort_in_scratch(int dtype, const void* keys_in, void* keys_out, int64_t n, const evosort_params* p,
+                               hipStream_t s, void* scratch, size_t scratch_bytes);
+
+// Records e as this thread's last HIP error; returns EVOSORT_ERR_HIP.
+evosort_status record_hip_failure(hipError_t e);
+
 }  // namespace evosort
