@@ -476,6 +476,23 @@ const char *evosort_build_id(void);
 evosort_status evosort_check_device_error(const void *temp, size_t temp_bytes, void *stream);
 
 /*
+ * Streaming kernels that bound the sort kernels from above, for measuring
+ * them (the roofline every radix pass and histogram is compared against):
+ *   evosort_stream_copy  reads and writes every byte once (16-byte accesses,
+ *                        a grid-stride loop), like one radix pass; `bytes` a
+ *                        multiple of 4; the library's own device-to-device
+ *                        copies use the same kernel.  dst and src must not
+ *                        overlap (EVOSORT_ERR_INVALID_ARG).
+ *   evosort_stream_read  reads every byte once and writes (almost) nothing,
+ *                        like the all-pass histogram; `bytes` a multiple of
+ *                        16, src 16-byte aligned; `sink` is one device word it
+ *                        may write.
+ * Both are enqueued on `stream` like the sorts.
+ */
+evosort_status evosort_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
+evosort_status evosort_stream_read(const void *src, size_t bytes, uint64_t *sink, void *stream);
+
+/*
  * Kernel timing with HIP events.  While enabled, every kernel launch of the
  * library is bracketed by two events recorded on the launch stream.
  * evosort_profile_collect synchronizes those events and folds them into

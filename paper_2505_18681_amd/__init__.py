@@ -59,7 +59,7 @@ EXPORTED = (
     "evosort_server_default_config", "evosort_server_create", "evosort_server_destroy", "evosort_server_submit",
     "evosort_server_result", "evosort_server_wait", "evosort_server_copy_out", "evosort_server_times",
     "evosort_server_release", "evosort_server_drain", "evosort_server_get_stats", "evosort_build_id",
-    "evosort_sort_noalloc",
+    "evosort_sort_noalloc", "evosort_stream_copy", "evosort_stream_read",
 )
 
 
@@ -139,6 +139,10 @@ _lib.evosort_sort_pairs.argtypes = [_i32, _vp, _vp, _vp, _vp, _u32, _i64, _vp, _
 _lib.evosort_argsort.argtypes = [_i32, _vp, _vp, _u32, _i64, _vp, _sz, _P, _vp]
 _lib.evosort_sort_noalloc.argtypes = [_i32, _vp, _vp, _i64, _P, _vp]
 _lib.evosort_sort_noalloc.restype = ctypes.c_int
+_lib.evosort_stream_copy.argtypes = [_vp, _vp, _sz, _vp]
+_lib.evosort_stream_copy.restype = ctypes.c_int
+_lib.evosort_stream_read.argtypes = [_vp, _sz, _vp, _vp]
+_lib.evosort_stream_read.restype = ctypes.c_int
 _lib.evosort_radix_histogram.argtypes = [_i32, _vp, _i64, _u32, _vp, _vp, _vp, _sz, _vp]
 _lib.evosort_radix_pass.argtypes = [_i32, _vp, _vp, _vp, _vp, _u32, _i64, _u32, _vp, _sz, _P, _vp]
 _lib.evosort_merge_block_sort.argtypes = [_i32, _vp, _vp, _vp, _vp, _u32, _i64, _P, ctypes.POINTER(_i64), _vp]
@@ -729,6 +733,28 @@ class Server:
         s = ServerStats()
         _check("evosort_server_get_stats", _lib.evosort_server_get_stats(self._h, ctypes.byref(s)))
         return {name: int(getattr(s, name)) for name, _ in ServerStats._fields_}
+
+
+# -------------------------------------------------------- streaming ceilings --
+def stream_copy(dst, src, *, stream=None):
+    """``evosort_stream_copy``: copy tensor ``src`` into ``dst`` (same number of bytes) with the library's
+    streaming copy kernel (reads and writes every byte once)."""
+    torch = _torch()
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("dst and src must be contiguous and of the same size in bytes")
+    with torch.cuda.device(src.device):
+        _check("evosort_stream_copy", _lib.evosort_stream_copy(_ptr(dst), _ptr(src), nbytes,
+                                                               _stream(src.device, stream)))
+    return dst
+
+
+def stream_read(src, sink, *, stream=None):
+    """``evosort_stream_read``: read every byte of ``src`` once (``sink``: an 8-byte device tensor)."""
+    torch = _torch()
+    with torch.cuda.device(src.device):
+        _check("evosort_stream_read", _lib.evosort_stream_read(_ptr(src), src.numel() * src.element_size(),
+                                                               _ptr(sink), _stream(src.device, stream)))
 
 
 # --------------------------------------------------------------- profiling --

@@ -267,7 +267,7 @@ struct Plan {
     uint32_t debug_flags;
     uint32_t t_ins;
     // radix scratch layout (byte offsets into temp)
-    size_t off_keys_a, off_keys_b, off_vals, off_hist, off_bases, off_status, off_ctr, off_err, off_blocks;
+    size_t off_keys_a, off_keys_b, off_vals, off_hist, off_bases, off_status, off_ctr, off_err, off_blocks, off_live;
     bool prefix0;  // pass 0 takes its tile offsets from the histogram's per-tile counts
     size_t zero_begin, zero_end;
     size_t status_pass_bytes;
@@ -396,7 +396,8 @@ evosort_status make_plan(int op, int dtype, int64_t n, uint32_t value_bytes, con
         // zeroed on every call: header (error word, tile counters), histograms, look-back words
         P->zero_begin = 0;
         P->off_err = 0;
-        P->off_ctr = 16;  // passes * 4 <= 64 bytes
+        P->off_ctr = 16;    // passes * 4 <= 64 bytes
+        P->off_live = 128;  // passes words, written by the scan
         off = kAlign;
         P->off_hist = off;
         off = align_up(off + (size_t)passes * bins * 8);
@@ -506,9 +507,13 @@ namespace {
 unsigned char* at(void* temp, size_t off) { return reinterpret_cast<unsigned char*>(temp) + off; }
 
 // ------------------------------------------------------------ radix path ----
-// Buffers: src keys (read only), out keys (may equal src), keys_a/keys_b in
-// temp; values likewise.  The pass buffers alternate so that the last pass
-// lands in the output; an odd pass count sorted in place needs one copy.
+// Buffers: the input keys (read only unless sorted in place), the output, and
+// one (argsort: two) key buffer(s) in temp; values likewise.  Every pass is
+// launched; on the device each pass learns from the scan which passes have a
+// digit that varies, skips itself if its digit is constant, and otherwise
+// picks its input and output so that the last live pass writes the output
+// (RadixRoute).  A final launch does the copy that an odd number of live
+// passes sorted in place, or no live pass at all, leaves to do.
 evosort_status run_radix(const Plan& P, const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
                          void* temp, hipStream_t s)
 {
@@ -520,6 +525,7 @@ evosort_status run_radix(const Plan& P, const void* keys_in, void* keys_out, con
     auto* bases = reinterpret_cast<uint64_t*>(at(temp, P.off_bases));
     auto* ctr = reinterpret_cast<uint32_t*>(at(temp, P.off_ctr));
     auto* err = reinterpret_cast<uint32_t*>(at(temp, P.off_err));
+    auto* live = reinterpret_cast<uint32_t*>(at(temp, P.off_live));
 
     EVOSORT_LAUNCH("fill_zero", s, launch_fill_zero(at(temp, P.zero_begin), P.zero_end - P.zero_begin, s));
     if (P.prefix0) {
@@ -533,48 +539,27 @@ evosort_status run_radix(const Plan& P, const void* keys_in, void* keys_out, con
     } else {
         EVOSORT_LAUNCH("radix_histogram", s, launch_radix_histogram(P.kd, keys_in, n, P.bits, passes, hist, s));
     }
-    EVOSORT_LAUNCH("radix_scan", s, launch_radix_scan(hist, bases, P.bits, passes, s));
+    EVOSORT_LAUNCH("radix_scan", s, launch_radix_scan(hist, bases, P.bits, passes, live, s));
 
     const bool argsort = P.op == EVOSORT_OP_ARGSORT;
-    void* ta = at(temp, P.off_keys_a);
-    void* tb = argsort ? at(temp, P.off_keys_b) : nullptr;
-    void* tv = vb ? at(temp, P.off_vals) : nullptr;
+    const bool pairs = P.op == EVOSORT_OP_SORT_PAIRS;
+    RadixRoute r{};
+    r.live = live;
+    r.passes = (uint32_t)passes;
+    r.flags = argsort ? ROUTE_ARGSORT : 0u;
+    // sorted in place: the first live pass must not write the output it reads
+    if (!argsort && (keys_out == keys_in || (pairs && vals_out == vals_in)))
+        r.flags |= ROUTE_COPY_IF_ODD;
+    r.keys_in = keys_in;
+    r.keys_out = argsort ? nullptr : keys_out;
+    r.keys_tmp = at(temp, P.off_keys_a);
+    r.keys_tmp2 = argsort ? at(temp, P.off_keys_b) : nullptr;
+    r.vals_in = pairs ? vals_in : nullptr;
+    r.vals_out = vb ? vals_out : nullptr;
+    r.vals_tmp = vb ? at(temp, P.off_vals) : nullptr;
 
-    // Destination of pass p: alternate between X and Y where the last pass
-    // writes the output.  For keys: X = out, Y = temp (argsort: temp a/b).
-    const bool in_place_keys = !argsort && keys_out == keys_in;
-    const bool in_place_vals = P.op == EVOSORT_OP_SORT_PAIRS && vals_out == vals_in;
-    // With the last pass writing `out`, pass 0 writes `out` iff passes is odd.
-    // Writing `out` in pass 0 is not allowed when it aliases the input.
-    const bool odd = (passes & 1) != 0;
-    const bool extra_copy = odd && (in_place_keys || in_place_vals);
-
-    const void* ksrc = keys_in;
-    const void* vsrc = vals_in;
     for (int p = 0; p < passes; ++p) {
-        const bool last = p == passes - 1;
-        // parity: which buffer this pass writes
-        const bool to_out = extra_copy ? false : (((passes - 1 - p) & 1) == 0);
-        void* kdst;
-        void* vdst = nullptr;
-        if (argsort) {
-            kdst = (p & 1) ? tb : ta;  // keys never reach an output
-            vdst = to_out ? vals_out : tv;
-        } else {
-            kdst = to_out ? keys_out : ta;
-            if (extra_copy)
-                kdst = (p & 1) ? keys_out : ta;
-            if (vb) {
-                vdst = to_out ? vals_out : tv;
-                if (extra_copy)
-                    vdst = (p & 1) ? vals_out : tv;
-            }
-        }
         RadixPassArgs a{};
-        a.keys_in = ksrc;
-        a.keys_out = kdst;
-        a.vals_in = vsrc;
-        a.vals_out = vdst;
         a.n = n;
         a.shift = (uint32_t)(p * P.bits);
         a.bases = bases + (size_t)p * bins;
@@ -583,28 +568,19 @@ evosort_status run_radix(const Plan& P, const void* keys_in, void* keys_out, con
         a.error_word = err;
         a.host_error = P.host_error;
         a.flags = 0;
-        if (argsort && p == 0)
-            a.flags |= RADIX_FLAG_IOTA;
-        if (argsort && last)
-            a.flags |= RADIX_FLAG_SKIP_KEYS;
         if (P.debug_flags & EVOSORT_DEBUG_WITHHOLD_TILE0)
             a.flags |= RADIX_FLAG_WITHHOLD_T0;
         if (p == 0 && P.prefix0)
-            a.flags |= RADIX_FLAG_PREFIX;
+            a.flags |= RADIX_FLAG_PREFIX;  // pass 0, when live, is the first live pass: it reads the input
         a.spin_limit = P.spin_limit;
         a.tiles = (uint32_t)P.info.tiles;
+        a.route = r;
+        a.route.pass = (uint32_t)p;
         EVOSORT_LAUNCH("radix_pass", s,
                        launch_radix_pass(P.kd, vb, P.bits, P.shape, (int)P.info.status_bytes, a,
                                          (uint32_t)P.info.tiles, s));
-        ksrc = kdst;
-        vsrc = vdst;
     }
-    if (extra_copy) {
-        // odd pass count, in place: the last pass wrote temp
-        EVOSORT_LAUNCH("copy", s, launch_copy(keys_out, ksrc, (size_t)n * kb, s));
-        if (vb)
-            EVOSORT_LAUNCH("copy", s, launch_copy(vals_out, vsrc, (size_t)n * vb, s));
-    }
+    EVOSORT_LAUNCH("radix_finish", s, launch_radix_finish(r, n, kb, vb, s));
     return EVOSORT_OK;
 }
 
@@ -1187,7 +1163,7 @@ evosort_status evosort_radix_histogram(int dtype, const void* keys, int64_t n, u
     if (n > 0)
         EVOSORT_LAUNCH("radix_histogram", s, launch_radix_histogram(kd, keys, n, bits, passes, hist_out, s));
     if (bases_out)
-        EVOSORT_LAUNCH("radix_scan", s, launch_radix_scan(hist_out, bases_out, bits, passes, s));
+        EVOSORT_LAUNCH("radix_scan", s, launch_radix_scan(hist_out, bases_out, bits, passes, nullptr, s));
     return EVOSORT_OK;
 }
 
@@ -1226,7 +1202,7 @@ evosort_status evosort_radix_pass(int dtype, const void* keys_in, void* keys_out
     EVOSORT_LAUNCH("fill_zero", s, launch_fill_zero(at(temp, P.zero_begin), P.zero_end - P.zero_begin, s));
     EVOSORT_LAUNCH("radix_histogram", s,
                    launch_radix_histogram(P.kd, keys_in, n, P.bits, (int)P.info.passes, hist, s));
-    EVOSORT_LAUNCH("radix_scan", s, launch_radix_scan(hist, bases, P.bits, (int)P.info.passes, s));
+    EVOSORT_LAUNCH("radix_scan", s, launch_radix_scan(hist, bases, P.bits, (int)P.info.passes, nullptr, s));
     RadixPassArgs a{};
     a.keys_in = keys_in;
     a.keys_out = keys_out;
@@ -1478,6 +1454,28 @@ evosort_status evosort_check_device_error(const void* temp, size_t temp_bytes, v
     if (word != 0)
         (void)take_pending_error();  // this failure is now reported; the next call need not repeat it
     return status_of_error_bits(word);
+}
+
+evosort_status evosort_stream_copy(void* dst, const void* src, size_t bytes, void* stream)
+{
+    if (bytes == 0)
+        return EVOSORT_OK;
+    if (!dst || !src || (bytes & 3) || overlaps(dst, bytes, src, bytes))
+        return EVOSORT_ERR_INVALID_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    EVOSORT_LAUNCH("stream_copy", s, launch_copy(dst, src, bytes, s));
+    return EVOSORT_OK;
+}
+
+evosort_status evosort_stream_read(const void* src, size_t bytes, uint64_t* sink, void* stream)
+{
+    if (bytes == 0)
+        return EVOSORT_OK;
+    if (!src || !sink || (bytes & 15) || ((uintptr_t)src & 15))
+        return EVOSORT_ERR_INVALID_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    EVOSORT_LAUNCH("stream_read", s, launch_stream_read(src, bytes, sink, s));
+    return EVOSORT_OK;
 }
 
 void evosort_profile_enable(int on)

@@ -37,8 +37,42 @@ hipError_t launch_radix_histogram_tiles(const KeyDesc& kd, const void* keys, int
 hipError_t launch_tile_prefix(void* counts, int status_bytes, uint32_t tiles, uint64_t* block_sums, hipStream_t s);
 constexpr uint32_t kTilePrefixBlock = 64;  // tiles per workgroup of the prefix kernels
 
-// Exclusive prefix sums of each pass's 2^bits histogram row.
-hipError_t launch_radix_scan(const uint64_t* hist, uint64_t* bases, int bits, int passes, hipStream_t s);
+// Exclusive prefix sums of each pass's 2^bits histogram row.  With `live`
+// (passes words) it also records, per pass, 1 if the pass's digit takes more
+// than one value over the keys and 0 if every key has the same digit there
+// (such a pass would leave the order unchanged).
+hipError_t launch_radix_scan(const uint64_t* hist, uint64_t* bases, int bits, int passes, uint32_t* live,
+                             hipStream_t s);
+
+// Buffers of a whole radix sort, from which each pass picks its input and
+// output on the device once the live passes are known (the scan's `live`
+// words): the launch sequence stays the same whatever digits are constant.
+// Live pass j (0-based among the m live passes) reads what live pass j - 1
+// wrote (the input for j = 0) and writes
+//   keys-only / pairs:  the output when m - 1 - j is even, else the
+//                       temporary buffer; with ROUTE_COPY_IF_ODD (sorting in
+//                       place) and m odd, the temporary buffer when j is even
+//                       and the output when j is odd, and the finishing launch
+//                       copies the temporary buffer to the output;
+//   argsort:            keys to keys_tmp (j even) or keys_tmp2 (j odd), never
+//                       the last live pass; indices as pairs' values, the
+//                       first live pass taking the input positions.
+// With no live pass the finishing launch copies the input to the output
+// (argsort: writes the identity permutation).
+struct RadixRoute {
+    const uint32_t* live;  // null: no routing, the pass reads and writes the RadixPassArgs buffers
+    uint32_t pass, passes;
+    uint32_t flags;        // ROUTE_*
+    const void* keys_in;
+    void* keys_out;
+    void* keys_tmp;
+    void* keys_tmp2;       // argsort only
+    const void* vals_in;   // pairs only
+    void* vals_out;        // values or indices
+    void* vals_tmp;
+};
+constexpr uint32_t ROUTE_ARGSORT = 1u;
+constexpr uint32_t ROUTE_COPY_IF_ODD = 2u;
 
 struct RadixPassArgs {
     const void* keys_in;
@@ -55,6 +89,7 @@ struct RadixPassArgs {
     uint32_t flags;          // RADIX_FLAG_*
     uint32_t spin_limit;
     uint32_t tiles;          // workgroups launched (= tiles of the pass)
+    RadixRoute route;        // route.live non-null: buffers and IOTA/SKIP_KEYS flags come from the route
 };
 constexpr uint32_t RADIX_FLAG_IOTA = 1u;          // values are the input positions (argsort, first pass)
 constexpr uint32_t RADIX_FLAG_SKIP_KEYS = 2u;     // do not write keys (argsort, last pass)
@@ -74,6 +109,10 @@ RadixShape radix_default_shape(int key_bytes, int val_bytes, int bits);
 RadixShape radix_default_shape_for(int key_bytes, int val_bytes, int bits, int64_t n);
 // Whether a single-sweep pass kernel exists for these parameters.
 bool radix_pass_available(int key_bytes, int val_bytes, int bits, RadixShape shape, int status_bytes);
+// The launch after the passes of a routed sort: the copy (or identity
+// permutation) that the live passes leave to do, if any; n keys of key_bytes,
+// values or indices of val_bytes.
+hipError_t launch_radix_finish(const RadixRoute& r, int64_t n, int key_bytes, int val_bytes, hipStream_t s);
 hipError_t launch_radix_pass(const KeyDesc& kd, int val_bytes, int bits, RadixShape shape, int status_bytes,
                              const RadixPassArgs& a, uint32_t tiles, hipStream_t s);
 
@@ -82,7 +121,11 @@ hipError_t launch_radix_pass(const KeyDesc& kd, int val_bytes, int bits, RadixSh
 // Zero `bytes` bytes at p (16-byte stores when p and bytes allow).
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
-// Copy `bytes` bytes device to device (a runtime copy on stream s).
+// Copy `bytes` bytes (a multiple of 4) device to device with the library's
+// streaming copy kernel.
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// Read `bytes` bytes (a multiple of 16, 16-byte aligned) once, writing
+// (almost) nothing: the ceiling of a read-only kernel.  sink: one device word.
+hipError_t launch_stream_read(const void* src, size_t bytes, uint64_t* sink, hipStream_t s);
 
 }  // namespace evosort

@@ -156,9 +156,10 @@ hipError_t launch_tile_prefix(void* counts, int status_bytes, uint32_t tiles, ui
     return hipGetLastError();
 }
 
-hipError_t launch_radix_scan(const uint64_t* hist, uint64_t* bases, int bits, int passes, hipStream_t s)
+hipError_t launch_radix_scan(const uint64_t* hist, uint64_t* bases, int bits, int passes, uint32_t* live,
+                             hipStream_t s)
 {
-    hipLaunchKernelGGL((radix_scan_kernel<256>), dim3(passes), dim3(256), 0, s, hist, bases, 1 << bits);
+    hipLaunchKernelGGL((radix_scan_kernel<256>), dim3(passes), dim3(256), 0, s, hist, bases, 1 << bits, live);
     return hipGetLastError();
 }
 
@@ -324,11 +325,159 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- streams --
+// Streaming copy and read: every byte moved once, 16-byte accesses with four
+// of them in flight per thread, a grid-stride loop over the range.  The copy
+// is the library's device-to-device copy; both are also the practical
+// ceilings the radix pass (read and write once) and the histogram (read
+// once) are measured against.
+constexpr int kStreamThreads = 256;
+constexpr int kStreamUnroll = 4;
+
+uint32_t stream_grid(size_t bytes)
+{
+    const size_t per_group = (size_t)kStreamThreads * kStreamUnroll * 16;
+    size_t g = (bytes + per_group - 1) / per_group;
+    if (g < 1)
+        g = 1;
+    if (g > 16384)
+        g = 16384;
+    return (uint32_t)g;
+}
+
+// bytes is a multiple of 4 (keys, values and indices are 4 or 8 bytes).
+__device__ __forceinline__ void copy_range(unsigned char* __restrict__ dst, const unsigned char* __restrict__ src,
+                                           size_t bytes, size_t tid, size_t nthreads)
+{
+    size_t done = 0;
+    if (((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15) == 0) {
+        const size_t n16 = bytes / 16;
+        uint4* d = reinterpret_cast<uint4*>(dst);
+        const uint4* s = reinterpret_cast<const uint4*>(src);
+        size_t i = tid;
+        for (; i + (kStreamUnroll - 1) * nthreads < n16; i += kStreamUnroll * nthreads) {
+            uint4 w[kStreamUnroll];
+#pragma unroll
+            for (int u = 0; u < kStreamUnroll; ++u)
+                w[u] = s[i + u * nthreads];
+#pragma unroll
+            for (int u = 0; u < kStreamUnroll; ++u)
+                d[i + u * nthreads] = w[u];
+        }
+        for (; i < n16; i += nthreads)
+            d[i] = s[i];
+        done = n16 * 16;
+    }
+    uint32_t* d4 = reinterpret_cast<uint32_t*>(dst + done);
+    const uint32_t* s4 = reinterpret_cast<const uint32_t*>(src + done);
+    for (size_t i = tid; i < (bytes - done) / 4; i += nthreads)
+        d4[i] = s4[i];
+}
+
+__global__ __launch_bounds__(kStreamThreads) void stream_copy_kernel(unsigned char* dst, const unsigned char* src,
+                                                                     size_t bytes)
+{
+    copy_range(dst, src, bytes, (size_t)blockIdx.x * kStreamThreads + threadIdx.x,
+               (size_t)gridDim.x * kStreamThreads);
+}
+
+// Reads every 16-byte word once (bytes: a multiple of 16, 16-byte aligned)
+// and folds it into one word per thread; a thread stores its word only when it
+// equals a value a real input practically never produces, so the loads cannot
+// be dropped and the kernel writes (almost) nothing.
+__global__ __launch_bounds__(kStreamThreads) void stream_read_kernel(const uint4* __restrict__ src, size_t n16,
+                                                                     unsigned long long* sink)
+{
+    const size_t nthreads = (size_t)gridDim.x * kStreamThreads;
+    size_t i = (size_t)blockIdx.x * kStreamThreads + threadIdx.x;
+    uint32_t acc = 0;
+    for (; i + (kStreamUnroll - 1) * nthreads < n16; i += kStreamUnroll * nthreads) {
+        uint4 w[kStreamUnroll];
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u)
+            w[u] = src[i + u * nthreads];
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u)
+            acc = (acc * 31u) ^ w[u].x ^ w[u].y ^ w[u].z ^ w[u].w;
+    }
+    for (; i < n16; i += nthreads) {
+        const uint4 w = src[i];
+        acc = (acc * 31u) ^ w.x ^ w.y ^ w.z ^ w.w;
+    }
+    if (acc == 0x9E3779B9u)
+        sink[0] = acc;
+}
+
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s)
 {
     if (bytes == 0 || dst == src)
         return hipSuccess;
-    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+    if (bytes & 3)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(stream_copy_kernel, dim3(stream_grid(bytes)), dim3(kStreamThreads), 0, s,
+                       reinterpret_cast<unsigned char*>(dst), reinterpret_cast<const unsigned char*>(src), bytes);
+    return hipGetLastError();
+}
+
+// After the passes of a routed sort (see RadixRoute): with no live pass, the
+// input goes to the output unchanged (argsort: the identity permutation);
+// with an odd number of live passes sorted in place, the last pass's
+// temporary buffer goes to the output; otherwise every workgroup leaves.
+__global__ __launch_bounds__(kStreamThreads) void radix_finish_kernel(RadixRoute r, int64_t n, int kb, int vb)
+{
+    uint32_t m = 0;
+    for (uint32_t q = 0; q < r.passes; ++q)
+        m += r.live[q];
+    const size_t tid = (size_t)blockIdx.x * kStreamThreads + threadIdx.x;
+    const size_t nth = (size_t)gridDim.x * kStreamThreads;
+    const bool argsort = (r.flags & ROUTE_ARGSORT) != 0;
+    if (m == 0) {
+        if (argsort) {
+            if (vb == 4) {
+                for (size_t i = tid; i < (size_t)n; i += nth)
+                    reinterpret_cast<uint32_t*>(r.vals_out)[i] = (uint32_t)i;
+            } else {
+                for (size_t i = tid; i < (size_t)n; i += nth)
+                    reinterpret_cast<uint64_t*>(r.vals_out)[i] = (uint64_t)i;
+            }
+            return;
+        }
+        if (r.keys_out != r.keys_in)
+            copy_range(reinterpret_cast<unsigned char*>(r.keys_out), reinterpret_cast<const unsigned char*>(r.keys_in),
+                       (size_t)n * kb, tid, nth);
+        if (vb && r.vals_out != r.vals_in)
+            copy_range(reinterpret_cast<unsigned char*>(r.vals_out), reinterpret_cast<const unsigned char*>(r.vals_in),
+                       (size_t)n * vb, tid, nth);
+        return;
+    }
+    if (!argsort && (r.flags & ROUTE_COPY_IF_ODD) && (m & 1)) {
+        copy_range(reinterpret_cast<unsigned char*>(r.keys_out), reinterpret_cast<const unsigned char*>(r.keys_tmp),
+                   (size_t)n * kb, tid, nth);
+        if (vb)
+            copy_range(reinterpret_cast<unsigned char*>(r.vals_out), reinterpret_cast<const unsigned char*>(r.vals_tmp),
+                       (size_t)n * vb, tid, nth);
+    }
+}
+
+hipError_t launch_radix_finish(const RadixRoute& r, int64_t n, int key_bytes, int val_bytes, hipStream_t s)
+{
+    if (n <= 0 || !r.live)
+        return hipSuccess;
+    hipLaunchKernelGGL(radix_finish_kernel, dim3(stream_grid((size_t)n * (key_bytes > val_bytes ? key_bytes : val_bytes))),
+                       dim3(kStreamThreads), 0, s, r, n, key_bytes, val_bytes);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_read(const void* src, size_t bytes, uint64_t* sink, hipStream_t s)
+{
+    if (bytes == 0)
+        return hipSuccess;
+    if ((bytes & 15) || (reinterpret_cast<uintptr_t>(src) & 15))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(stream_read_kernel, dim3(stream_grid(bytes)), dim3(kStreamThreads), 0, s,
+                       reinterpret_cast<const uint4*>(src), bytes / 16,
+                       reinterpret_cast<unsigned long long*>(sink));
+    return hipGetLastError();
 }
 
 }  // namespace evosort

@@ -334,13 +334,19 @@ __global__ __launch_bounds__(256) void tile_prefix_kernel(ST* __restrict__ count
 }
 
 // ------------------------------------------------------------------------
-// Digit bases: exclusive scan of one histogram row per workgroup
+// Digit bases: exclusive scan of one histogram row per workgroup; with
+// `live`, whether the row's pass has more than one digit value (a row whose
+// whole count sits in one digit leaves the order unchanged: its pass can go)
 // ------------------------------------------------------------------------
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void radix_scan_kernel(const uint64_t* __restrict__ hist,
-                                                             uint64_t* __restrict__ bases, int bins)
+                                                             uint64_t* __restrict__ bases, int bins,
+                                                             uint32_t* __restrict__ live)
 {
     __shared__ uint64_t part[THREADS];
+    __shared__ uint32_t one_digit;
+    if (threadIdx.x == 0)
+        one_digit = 0;
     const uint64_t* row = hist + (size_t)blockIdx.x * bins;
     uint64_t* out = bases + (size_t)blockIdx.x * bins;
     const int per = (bins + THREADS - 1) / THREADS;
@@ -359,11 +365,18 @@ __global__ __launch_bounds__(THREADS) void radix_scan_kernel(const uint64_t* __r
         __syncthreads();
     }
     uint64_t run = part[threadIdx.x] - s;
+    const uint64_t total = part[THREADS - 1];
     for (int j = 0; j < per; ++j)
         if (b0 + j < bins) {
+            const uint64_t c = row[b0 + j];
             out[b0 + j] = run;
-            run += row[b0 + j];
+            run += c;
+            if (c == total)
+                one_digit = 1;  // every key has this digit
         }
+    __syncthreads();
+    if (live && threadIdx.x == 0)
+        live[blockIdx.x] = one_digit ? 0u : 1u;
 }
 
 // ------------------------------------------------------------------------
@@ -483,8 +496,19 @@ struct PassLds {
 // Everything a workgroup does for one tile after it has its tile number.
 // FULL: the tile holds TILE keys (every tile but possibly the last), so no
 // per-item validity is tracked.
+// The buffers and per-pass flags one pass works with (the kernel's own
+// arguments, or what the route picks for it).
+struct PassIo {
+    const void* keys_in;
+    void* keys_out;
+    const void* vals_in;
+    void* vals_out;
+    uint32_t flags;  // RADIX_FLAG_*
+};
+
 template <bool FULL, int KB, int VB, int BITS, int THREADS, int ITEMS, typename ST>
-__device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap<typename KeyWord<KB>::U>& om,
+__device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const PassIo& io,
+                                          const OrderMap<typename KeyWord<KB>::U>& om,
                                           PassLds<KB, VB, BITS, THREADS, ITEMS>& L, uint32_t tile, int64_t tile_start,
                                           uint32_t nvalid)
 {
@@ -508,7 +532,7 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
     const int w = threadIdx.x / kWave;
     // Offsets inside the tile are 32-bit; only the tile base is 64-bit.
     const uint32_t off0 = (uint32_t)(w * WAVE_KEYS + lane);
-    const U* __restrict__ tile_keys = reinterpret_cast<const U*>(a.keys_in) + tile_start;
+    const U* __restrict__ tile_keys = reinterpret_cast<const U*>(io.keys_in) + tile_start;
     // item i of this thread is valid iff i * 64 < rem: one register for all
     // items instead of one offset per item
     const int32_t rem = FULL ? 0 : (int32_t)materialize(nvalid - off0);
@@ -525,8 +549,8 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
         k[i] = load_off32(tile_keys, FULL ? off : min(off, nvalid - 1));
     }
     if constexpr (VB != 0) {
-        const V* __restrict__ tile_vals = reinterpret_cast<const V*>(a.vals_in) + tile_start;
-        const bool iota = (a.flags & RADIX_FLAG_IOTA) != 0;
+        const V* __restrict__ tile_vals = reinterpret_cast<const V*>(io.vals_in) + tile_start;
+        const bool iota = (io.flags & RADIX_FLAG_IOTA) != 0;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t off = off0 + (uint32_t)(i * kWave);
@@ -639,8 +663,8 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
         cnt[j] = c;
         tsum += c;
     }
-    const bool prefixed = (a.flags & RADIX_FLAG_PREFIX) != 0;
-    const bool publish = !prefixed && !((a.flags & RADIX_FLAG_WITHHOLD_T0) && tile == 0);
+    const bool prefixed = (io.flags & RADIX_FLAG_PREFIX) != 0;
+    const bool publish = !prefixed && !((io.flags & RADIX_FLAG_WITHHOLD_T0) && tile == 0);
     if (publish) {
         const ST flag = (ST)(tile == 0 ? kFlagInclusive : kFlagAggregate) << Status<ST>::kShift;
 #pragma unroll
@@ -730,9 +754,9 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
     __syncthreads();  // staged keys and per-digit output slots are in LDS
 
     // ---- coalesced write-out: consecutive threads, consecutive positions ----
-    const bool write_keys = !(a.flags & RADIX_FLAG_SKIP_KEYS);
-    U* __restrict__ keys_out = reinterpret_cast<U*>(a.keys_out);
-    V* __restrict__ vals_out = reinterpret_cast<V*>(a.vals_out);
+    const bool write_keys = !(io.flags & RADIX_FLAG_SKIP_KEYS);
+    U* __restrict__ keys_out = reinterpret_cast<U*>(io.keys_out);
+    V* __restrict__ vals_out = reinterpret_cast<V*>(io.vals_out);
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t p = (uint32_t)(i * THREADS) + threadIdx.x;
@@ -762,6 +786,40 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const OrderMap
     }
 }
 
+// A routed pass (see RadixRoute) picks its buffers from the live passes:
+// returns false when its own digit is constant (the whole pass is skipped).
+// The live words are the same for every workgroup and lane.
+__device__ __forceinline__ bool route_pass(const RadixRoute& r, PassIo& io)
+{
+    uint32_t j = 0, m = 0, me = 0;
+    for (uint32_t q = 0; q < r.passes; ++q) {
+        const uint32_t l = r.live[q];
+        m += l;
+        j += q < r.pass ? l : 0u;
+        me = q == r.pass ? l : me;
+    }
+    if (!me)
+        return false;
+    if (r.flags & ROUTE_ARGSORT) {
+        const bool to_out = ((m - 1 - j) & 1) == 0;
+        io.keys_in = j == 0 ? r.keys_in : (((j - 1) & 1) ? r.keys_tmp2 : r.keys_tmp);
+        io.keys_out = (j & 1) ? r.keys_tmp2 : r.keys_tmp;
+        io.vals_out = to_out ? r.vals_out : r.vals_tmp;
+        io.vals_in = j == 0 ? nullptr : (to_out ? r.vals_tmp : r.vals_out);
+        io.flags |= (j == 0 ? RADIX_FLAG_IOTA : 0u) | (j == m - 1 ? RADIX_FLAG_SKIP_KEYS : 0u);
+    } else {
+        // whether live pass jj writes the output (else the temporary buffer)
+        const bool odd_copy = (r.flags & ROUTE_COPY_IF_ODD) && (m & 1);
+        const bool out_now = odd_copy ? (j & 1) != 0 : ((m - 1 - j) & 1) == 0;
+        const bool out_before = j > 0 && (odd_copy ? ((j - 1) & 1) != 0 : ((m - j) & 1) == 0);
+        io.keys_out = out_now ? r.keys_out : r.keys_tmp;
+        io.keys_in = j == 0 ? r.keys_in : (out_before ? r.keys_out : r.keys_tmp);
+        io.vals_out = out_now ? r.vals_out : r.vals_tmp;
+        io.vals_in = j == 0 ? r.vals_in : (out_before ? r.vals_out : r.vals_tmp);
+    }
+    return true;
+}
+
 // One workgroup per tile.  The tile number is a ticket taken from an atomic
 // counter, not blockIdx: tickets are handed out in the order workgroups start
 // running, so a tile's look-back only ever waits on tiles whose workgroups are
@@ -775,6 +833,10 @@ __global__ __launch_bounds__(THREADS) void radix_pass_kernel(RadixPassArgs a, Or
     static_assert((1 << BITS) <= 4096, "digit field is 12 bits");
     __shared__ Lds L;
 
+    PassIo io{a.keys_in, a.keys_out, a.vals_in, a.vals_out, a.flags};
+    if (a.route.live && !route_pass(a.route, io))
+        return;  // uniform: this pass's digit is the same for every key
+
     if (threadIdx.x == 0)
         L.ticket = atomicAdd(a.tile_counter, 1u);
     __syncthreads();
@@ -784,9 +846,9 @@ __global__ __launch_bounds__(THREADS) void radix_pass_kernel(RadixPassArgs a, Or
     const int64_t tile_start = (int64_t)tile * TILE;
     const int64_t left = a.n - tile_start;
     if (left >= TILE)
-        pass_tile<true, KB, VB, BITS, THREADS, ITEMS, ST>(a, om, L, tile, tile_start, (uint32_t)TILE);
+        pass_tile<true, KB, VB, BITS, THREADS, ITEMS, ST>(a, io, om, L, tile, tile_start, (uint32_t)TILE);
     else
-        pass_tile<false, KB, VB, BITS, THREADS, ITEMS, ST>(a, om, L, tile, tile_start, (uint32_t)left);
+        pass_tile<false, KB, VB, BITS, THREADS, ITEMS, ST>(a, io, om, L, tile, tile_start, (uint32_t)left);
 }
 
 // One pass over the tiles of every large segment of a batched sort.  Tiles
@@ -823,11 +885,11 @@ __global__ __launch_bounds__(THREADS) void seg_radix_pass_kernel(SegPassArgs sa,
     g.len = __builtin_amdgcn_readfirstlane(g.len);
     g.first_tile = __builtin_amdgcn_readfirstlane(g.first_tile);
     RadixPassArgs a = sa.base;
-    a.keys_in = reinterpret_cast<const U*>(sa.base.keys_in) + g.begin;
-    a.keys_out = reinterpret_cast<U*>(sa.base.keys_out) + g.begin;
+    PassIo io{reinterpret_cast<const U*>(sa.base.keys_in) + g.begin, reinterpret_cast<U*>(sa.base.keys_out) + g.begin,
+              nullptr, nullptr, sa.base.flags};
     if constexpr (VB != 0) {
-        a.vals_in = reinterpret_cast<const V*>(sa.base.vals_in) + g.begin;
-        a.vals_out = reinterpret_cast<V*>(sa.base.vals_out) + g.begin;
+        io.vals_in = reinterpret_cast<const V*>(sa.base.vals_in) + g.begin;
+        io.vals_out = reinterpret_cast<V*>(sa.base.vals_out) + g.begin;
     }
     a.n = g.len;
     a.bases = sa.base.bases + (size_t)slot * sa.slot_stride;
@@ -836,9 +898,9 @@ __global__ __launch_bounds__(THREADS) void seg_radix_pass_kernel(SegPassArgs sa,
     const int64_t tile_start = (int64_t)lt * TILE;
     const int64_t left = (int64_t)g.len - tile_start;
     if (left >= TILE)
-        pass_tile<true, KB, VB, BITS, THREADS, ITEMS, ST>(a, om, L, lt, tile_start, (uint32_t)TILE);
+        pass_tile<true, KB, VB, BITS, THREADS, ITEMS, ST>(a, io, om, L, lt, tile_start, (uint32_t)TILE);
     else
-        pass_tile<false, KB, VB, BITS, THREADS, ITEMS, ST>(a, om, L, lt, tile_start, (uint32_t)left);
+        pass_tile<false, KB, VB, BITS, THREADS, ITEMS, ST>(a, io, om, L, lt, tile_start, (uint32_t)left);
 }
 
 template <int KB, int VB, int BITS, int THREADS, int ITEMS, typename ST>
