@@ -411,24 +411,30 @@ def run_serving_bench(es, torch, count: int, rate: float, budget_gb: float, seed
             "plain_fifo": plain}
 
 
-def copy_bandwidth(torch, nbytes: int = 4 << 30, reps: int = 10) -> float:
-    """Read + write GB/s of a plain device-to-device copy of `nbytes` (PyTorch's copy kernel), timed with
-    HIP events: the practical ceiling of a kernel that reads and writes every byte once."""
+def stream_ceilings(es, torch, nbytes: int = 4 << 30, reps: int = 10) -> dict:
+    """The library's hand-written streaming kernels on `nbytes` of HBM, timed with HIP events: the copy (reads
+    and writes every byte once, like a radix pass) and the read (reads every byte once, like the histogram).
+    Rates count bytes read plus bytes written; these are the practical ceilings of the two kernel kinds."""
     src = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
     dst = torch.empty_like(src)
-    for _ in range(2):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / reps
-    del src, dst
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = {}
+    for name, fn, moved in (("copy_gbs", lambda: es.stream_copy(dst, src), 2 * nbytes),
+                            ("read_gbs", lambda: es.stream_read(src, sink), nbytes)):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        out[name] = round(moved / (ms * 1e-3) / 1e9, 1)
+    del src, dst, sink
     torch.cuda.empty_cache()
-    return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
+    return out
 
 
 def run_paper_sweep(es, torch, n: int, seed: int, steps: int = 5):
@@ -592,6 +598,24 @@ def run_vendor_compare(es, torch, n: int, seed: int, steps: int = 3):
             "torch_version": torch.__version__}
 
 
+def host_cpu() -> dict:
+    """Host cores this process may use, and the CPU model from /proc/cpuinfo."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count()
+    return {"nproc": avail, "cpu_count": os.cpu_count(), "cpu_model": model}
+
+
 def cpu_baseline(dtype_name: str, n_sample: int, seed: int):
     """The oracle, untuned, on a bounded sample of the same workload (one host thread)."""
     import numpy as np
@@ -605,12 +629,149 @@ def cpu_baseline(dtype_name: str, n_sample: int, seed: int):
     out = keys[perm]
     dt = time.perf_counter() - t0
     del out, perm
+    host = host_cpu()
     return {"value": round(n_sample / dt / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
             "sample": f"{n_sample:.0e} {dtype_name} uniform keys (seed {seed}), stable mergesort, "
-                      f"{dt:.2f} s on one host thread"}
+                      f"{dt:.2f} s on one host thread",
+            "nproc": host["nproc"], "cpu_count": host["cpu_count"], "cpu_model": host["cpu_model"]}
+
+
+# ------------------------------------------------------- profile summaries --
+# rocprofv3 writes CSV files (--output-format csv); these turn a kernel trace
+# and two counter runs of this script into the markdown summaries kept under
+# profiles/ (python bench.py --summarize-trace DIR ... / --summarize-pmc DIR DIR ...).
+
+def _csv_rows(directory: str, suffix: str):
+    import csv
+    import glob
+
+    paths = sorted(glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True))
+    if not paths:
+        raise SystemExit(f"no *{suffix} under {directory}")
+    rows = []
+    for path in paths:
+        with open(path, newline="") as f:
+            rows.extend(csv.DictReader(f))
+    return rows
+
+
+def short_kernel_name(name: str) -> str:
+    """`void evosort::radix_pass_kernel<4, 0, ...>(args)` -> `radix_pass_kernel<4, 0, ...>`."""
+    name = name.strip()
+    for prefix in ("void ",):
+        if name.startswith(prefix):
+            name = name[len(prefix):]
+    depth, cut = 0, len(name)
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            cut = i
+            break
+    name = name[:cut].replace("evosort::", "")
+    return name if len(name) <= 64 else name[:61] + "..."
+
+
+def summarize_trace(trace_dir: str, kernel: str, skip: int, passes: int, bytes_per_launch: float,
+                    command: str, title: str) -> str:
+    """Markdown summary of a kernel trace: per-kernel statistics over every dispatch, then the dominant
+    kernel's launches without the first `skip` (the warm-up calls), by pass, and its roofline."""
+    rows = _csv_rows(trace_dir, "kernel_trace.csv")
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    per = {}
+    for r in rows:
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        per.setdefault(short_kernel_name(r["Kernel_Name"]), []).append(us)
+    total = sum(sum(v) for v in per.values())
+    lines = [f"# {title}", "", "Command (from the repository root on the GPU box):", "", "```", command, "```", "",
+             "| kernel | calls | avg (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
+    for name, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| `{name}` | {len(v)} | {sum(v) / len(v):.1f} | {min(v):.1f} | {max(v):.1f} | "
+                     f"{100 * sum(v) / total:.1f}% |")
+    dom = [(n, v) for n, v in per.items() if n.startswith(kernel)]
+    if len(dom) != 1:
+        raise SystemExit(f"kernel {kernel!r} matches {[n for n, _ in dom]}")
+    name, launches = dom[0]
+    timed = launches[skip:]
+    avg = sum(timed) / len(timed)
+    gbs = bytes_per_launch / (avg * 1e-6) / 1e9
+    lines += ["", f"Timed launches of `{name}`: {len(timed)} (the first {skip} of {len(launches)}, from the "
+              "warm-up calls, left out).", "", "| pass | launches | avg (us) | min (us) | max (us) |",
+              "|---|---|---|---|---|"]
+    for p in range(passes):
+        v = timed[p::passes]
+        if v:
+            lines.append(f"| {p} | {len(v)} | {sum(v) / len(v):.1f} | {min(v):.1f} | {max(v):.1f} |")
+    lines.append(f"| all | {len(timed)} | {avg:.1f} | {min(timed):.1f} | {max(timed):.1f} |")
+    rec = {"kernel": name, "timed_launches": len(timed), "avg_us": round(avg, 2),
+           "algorithmic_bytes_per_launch": bytes_per_launch, "achieved_gbs": round(gbs, 1),
+           "peak_gbs": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    lines += ["", f"Algorithmic bytes per launch {bytes_per_launch / 1e9:.3f} GB / {avg:.1f} us = {gbs:.1f} GB/s, "
+              f"{100 * gbs / HBM_PEAK_GBS:.1f} % of {HBM_PEAK_GBS:.0f} GB/s.", "",
+              "roofline_json: " + json.dumps(rec)]
+    return "\n".join(lines) + "\n"
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, kernel: str, bytes_per_launch: float, calib_bytes: int,
+                  dtype: str, n: int, commands: list, title: str) -> str:
+    """Markdown summary of two counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).  Both counters
+    are scaled by what they read for the largest dispatch of the library's streaming copy kernel, which
+    moves `calib_bytes` each way."""
+    counts = {}
+    for d, cname in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        per_dispatch = {}
+        for r in _csv_rows(d, "counter_collection.csv"):
+            if r["Counter_Name"] != cname:
+                continue
+            key = (short_kernel_name(r["Kernel_Name"]), int(r["Dispatch_Id"]))
+            per_dispatch[key] = per_dispatch.get(key, 0.0) + float(r["Counter_Value"])
+        counts[cname] = per_dispatch
+    calib = {c: max(v for (k, _), v in counts[c].items() if k.startswith("stream_copy_kernel"))
+             for c in ("FETCH_SIZE", "WRITE_SIZE")}
+    scale = {c: calib_bytes / (calib[c] * 1024.0) for c in calib}
+    lines = [f"# {title}", "", "Two counter runs, one counter each (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch):",
+             "", "```"] + commands + ["```", "",
+             f"Calibration: the largest dispatch of the library's streaming copy kernel moves {calib_bytes} bytes "
+             f"each way and reads FETCH_SIZE = {calib['FETCH_SIZE']:.0f} KiB, WRITE_SIZE = "
+             f"{calib['WRITE_SIZE']:.0f} KiB, so fetch counts are scaled by {scale['FETCH_SIZE']:.4f} and write "
+             f"counts by {scale['WRITE_SIZE']:.4f}.", "",
+             "| kernel | dispatches | FETCH_SIZE KiB per dispatch (raw) | WRITE_SIZE KiB per dispatch (raw) | "
+             "scaled HBM bytes per dispatch |", "|---|---|---|---|---|"]
+    names = {}
+    for c in counts:
+        for (k, _), v in counts[c].items():
+            names.setdefault(k, {}).setdefault(c, []).append(v)
+    dom = None
+    for k, by in sorted(names.items()):
+        f = by.get("FETCH_SIZE", [0.0])
+        w = by.get("WRITE_SIZE", [0.0])
+        fa, wa = sum(f) / len(f), sum(w) / len(w)
+        scaled = (fa * scale["FETCH_SIZE"] + wa * scale["WRITE_SIZE"]) * 1024.0
+        lines.append(f"| `{k}` | {len(f)} | {fa:.0f} | {wa:.0f} | {scaled / 1e9:.3f} GB |")
+        if k.startswith(kernel):
+            dom = (k, fa, wa, scaled, f, w)
+    if dom is None:
+        raise SystemExit(f"kernel {kernel!r} not in the counter runs")
+    k, fa, wa, scaled, f, w = dom
+    lines += ["", f"Per launch of `{k}`, in dispatch order: " + "; ".join(
+        f"{(a * scale['FETCH_SIZE'] + b * scale['WRITE_SIZE']) * 1024.0 / 1e9:.3f} GB" for a, b in zip(f, w)),
+        "", f"Algorithmic bytes per launch: {bytes_per_launch / 1e9:.3f} GB; counted (scaled) bytes per launch: "
+        f"{scaled / 1e9:.3f} GB ({scaled / bytes_per_launch:.3f}x).", "",
+        "Machine-readable line read by bench.py (`source_hash` = kernel sources the counters were taken on):", "",
+        "traffic_json: " + json.dumps({"kernel": k, "n": n, "dtype": dtype, "fetch_kib_raw": round(fa),
+                                       "write_kib_raw": round(wa), "fetch_scale": round(scale["FETCH_SIZE"], 4),
+                                       "write_scale": round(scale["WRITE_SIZE"], 4),
+                                       "bytes_per_launch": round(scaled),
+                                       "algorithmic_bytes_per_launch": bytes_per_launch,
+                                       "source_hash": kernel_source_hash()})]
+    return "\n".join(lines) + "\n"
 
 
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] in ("--summarize-trace", "--summarize-pmc"):
+        return summarize_main()
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -640,7 +801,7 @@ def main():
     ap.add_argument("--tuned-pop", type=int, default=10)
     ap.add_argument("--tuned-generations", type=int, default=4)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one plain 1 GiB device copy (for counter calibration runs)")
+                    help="also run one 1 GiB copy with the library's streaming copy kernel (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -722,13 +883,15 @@ def main():
               file=sys.stderr, flush=True)
 
     if args.copy_calibration:
-        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        # one 1 GiB copy with the library's streaming copy kernel: counter runs scale by what it reads
+        src = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        es.stream_copy(dst, src)
         torch.cuda.synchronize()
         del src, dst
 
-    copy_gbs = copy_bandwidth(torch)
+    ceilings = stream_ceilings(es, torch)
+    copy_gbs = ceilings["copy_gbs"]
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -771,6 +934,7 @@ def main():
             "algorithmic_bytes_per_launch": algorithmic_pass_bytes(args.n, kb),
             "mean_launch_ms": round(main_res["pass_mean_ms"], 4),
             "copy_gbs": copy_gbs,
+            "read_gbs": ceilings["read_gbs"],
             "frac_of_copy": round(achieved / copy_gbs, 4) if achieved and copy_gbs else None,
         },
         "cpu_baseline": cpu,
@@ -784,6 +948,28 @@ def main():
         "paper_sweep": paper_sweep,
     }
     print(json.dumps(line), flush=True)
+
+
+def summarize_main():
+    ap = argparse.ArgumentParser(description="Summarize rocprofv3 CSV output of this script as markdown")
+    ap.add_argument("--summarize-trace", metavar="DIR")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--kernel", default="radix_pass_kernel<4, 0, 8, 768, 24")
+    ap.add_argument("--skip", type=int, default=0, help="leading launches of the kernel to leave out (warm-up)")
+    ap.add_argument("--passes", type=int, default=4)
+    ap.add_argument("--bytes-per-launch", type=float, default=8e9)
+    ap.add_argument("--calib-bytes", type=int, default=4 << 30)
+    ap.add_argument("--dtype", default="int32")
+    ap.add_argument("--n", type=int, default=1_000_000_000)
+    ap.add_argument("--command", action="append", default=[], help="command line that produced the CSVs")
+    ap.add_argument("--title", default="")
+    a = ap.parse_args()
+    if a.summarize_trace:
+        print(summarize_trace(a.summarize_trace, a.kernel, a.skip, a.passes, a.bytes_per_launch,
+                              "\n".join(a.command), a.title), end="")
+    else:
+        print(summarize_pmc(a.summarize_pmc[0], a.summarize_pmc[1], a.kernel, a.bytes_per_launch, a.calib_bytes,
+                            a.dtype, a.n, a.command, a.title), end="")
 
 
 if __name__ == "__main__":

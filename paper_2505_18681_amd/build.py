@@ -11,6 +11,7 @@ from __future__ import annotations
 import concurrent.futures as cf
 import hashlib
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -31,6 +32,13 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE, "-I", CSRC,
 ]
+
+# Default tile shapes of the radix pass per (key bytes, value bytes) at 8-bit
+# digits (radix_default_shape_c in csrc/radix_shapes.hpp): their kernels must
+# not lose workgroups per CU to registers, and no radix pass may use scratch.
+DEFAULT_PASS_SHAPES = {(4, 0): (768, 24), (4, 4): (768, 24), (4, 8): (512, 24),
+                       (8, 0): (768, 12), (8, 4): (512, 24), (8, 8): (512, 16)}
+LDS_PER_CU = 160 * 1024
 
 UNITS = [
     ("radix_host.hip", "radix_host.o", []),
@@ -65,19 +73,61 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def _resource_usage(text: str) -> dict:
+    """Per kernel: the compiler's resource remarks (-Rpass-analysis=kernel-resource-usage)."""
+    usage, name = {}, None
+    for line in text.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            usage[name] = {}
+            continue
+        m = re.search(r"remark:\s+([A-Za-z ]+?)(?: \[[^\]]*\])?: (\d+)", line)
+        if name and m:
+            usage[name][m.group(1).strip()] = int(m.group(2))
+    return usage
+
+
+def _check_pass_kernels(usage: dict):
+    """No radix pass kernel spills to scratch; the default shapes keep every workgroup LDS allows per CU."""
+    bad = []
+    for name, u in usage.items():
+        m = re.search(r"radix_pass_kernelILi(\d+)ELi(\d+)ELi(\d+)ELi(\d+)ELi(\d+)E([jm])E", name)
+        if not m:
+            continue
+        kb, vb, bits, threads, items = (int(m.group(i)) for i in range(1, 6))
+        if u.get("ScratchSize", 0) > 0:
+            bad.append(f"{name}: {u['ScratchSize']} bytes of scratch per lane")
+        if bits == 8 and DEFAULT_PASS_SHAPES.get((kb, vb)) == (threads, items) and "LDS Size" in u:
+            by_lds = LDS_PER_CU // max(u["LDS Size"], 1)
+            waves = threads // 64
+            by_regs = (4 * u.get("Occupancy", 0)) // waves
+            if by_regs < min(by_lds, 8):
+                bad.append(f"{name}: {u.get('VGPRs')} VGPRs allow {by_regs} workgroups per CU, LDS allows {by_lds}")
+    if bad:
+        raise RuntimeError("radix pass kernels lost occupancy or spill:\n  " + "\n  ".join(bad))
+
+
 def _compile(unit, verbose, defines=()):
     src, obj, extra = unit
     out = os.path.join(BUILD, obj)
+    report = src == "radix_inst.hip"
     cmd = [HIPCC] + COMMON + list(defines) + extra + ["-c", os.path.join(CSRC, src), "-o", out]
+    if report:
+        cmd.append("-Rpass-analysis=kernel-resource-usage")
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     noise = "packed-fp32-ops"  # the host pass does not know the feature; harmless
-    msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if noise not in l and l.strip())
+    text = r.stdout + r.stderr
+    msgs = "\n".join(l for l in text.splitlines()
+                     if noise not in l and l.strip() and "kernel-resource-usage" not in l)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{msgs}")
     if msgs and verbose:
         print(msgs, flush=True)
+    if report:
+        _check_pass_kernels(_resource_usage(text))
     return out
 
 

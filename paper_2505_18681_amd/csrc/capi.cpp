@@ -267,7 +267,8 @@ struct Plan {
     uint32_t debug_flags;
     uint32_t t_ins;
     // radix scratch layout (byte offsets into temp)
-    size_t off_keys_a, off_keys_b, off_vals, off_hist, off_bases, off_status, off_ctr, off_err, off_blocks, off_live;
+    size_t off_keys_a, off_keys_b, off_vals, off_hist, off_bases, off_status, off_ctr, off_err, off_blocks, off_live,
+        off_done;
     bool prefix0;  // pass 0 takes its tile offsets from the histogram's per-tile counts
     size_t zero_begin, zero_end;
     size_t status_pass_bytes;
@@ -396,8 +397,9 @@ evosort_status make_plan(int op, int dtype, int64_t n, uint32_t value_bytes, con
         // zeroed on every call: header (error word, tile counters), histograms, look-back words
         P->zero_begin = 0;
         P->off_err = 0;
-        P->off_ctr = 16;    // passes * 4 <= 64 bytes
-        P->off_live = 128;  // passes words, written by the scan
+        P->off_live = 16;  // the live-pass word (zeroed here, bits set by the scan)
+        P->off_done = 20;  // scan workgroups finished
+        P->off_ctr = 64;   // 64-bit ticket counters: passes * 8 <= 128 bytes
         off = kAlign;
         P->off_hist = off;
         off = align_up(off + (size_t)passes * bins * 8);
@@ -523,9 +525,10 @@ evosort_status run_radix(const Plan& P, const void* keys_in, void* keys_out, con
     const int64_t n = P.n;
     auto* hist = reinterpret_cast<uint64_t*>(at(temp, P.off_hist));
     auto* bases = reinterpret_cast<uint64_t*>(at(temp, P.off_bases));
-    auto* ctr = reinterpret_cast<uint32_t*>(at(temp, P.off_ctr));
+    auto* tickets = reinterpret_cast<unsigned long long*>(at(temp, P.off_ctr));
     auto* err = reinterpret_cast<uint32_t*>(at(temp, P.off_err));
     auto* live = reinterpret_cast<uint32_t*>(at(temp, P.off_live));
+    auto* done = reinterpret_cast<uint32_t*>(at(temp, P.off_done));
 
     EVOSORT_LAUNCH("fill_zero", s, launch_fill_zero(at(temp, P.zero_begin), P.zero_end - P.zero_begin, s));
     if (P.prefix0) {
@@ -539,7 +542,7 @@ evosort_status run_radix(const Plan& P, const void* keys_in, void* keys_out, con
     } else {
         EVOSORT_LAUNCH("radix_histogram", s, launch_radix_histogram(P.kd, keys_in, n, P.bits, passes, hist, s));
     }
-    EVOSORT_LAUNCH("radix_scan", s, launch_radix_scan(hist, bases, P.bits, passes, live, s));
+    EVOSORT_LAUNCH("radix_scan", s, launch_radix_scan(hist, bases, P.bits, passes, live, done, tickets, s));
 
     const bool argsort = P.op == EVOSORT_OP_ARGSORT;
     const bool pairs = P.op == EVOSORT_OP_SORT_PAIRS;
@@ -564,7 +567,7 @@ evosort_status run_radix(const Plan& P, const void* keys_in, void* keys_out, con
         a.shift = (uint32_t)(p * P.bits);
         a.bases = bases + (size_t)p * bins;
         a.status = at(temp, P.off_status + (size_t)p * P.status_pass_bytes);
-        a.tile_counter = ctr + p;
+        a.ticket = tickets + p;
         a.error_word = err;
         a.host_error = P.host_error;
         a.flags = 0;
@@ -1163,7 +1166,8 @@ evosort_status evosort_radix_histogram(int dtype, const void* keys, int64_t n, u
     if (n > 0)
         EVOSORT_LAUNCH("radix_histogram", s, launch_radix_histogram(kd, keys, n, bits, passes, hist_out, s));
     if (bases_out)
-        EVOSORT_LAUNCH("radix_scan", s, launch_radix_scan(hist_out, bases_out, bits, passes, nullptr, s));
+        EVOSORT_LAUNCH("radix_scan", s, launch_radix_scan(hist_out, bases_out, bits, passes, nullptr, nullptr, nullptr,
+                                                          s));
     return EVOSORT_OK;
 }
 
@@ -1202,7 +1206,8 @@ evosort_status evosort_radix_pass(int dtype, const void* keys_in, void* keys_out
     EVOSORT_LAUNCH("fill_zero", s, launch_fill_zero(at(temp, P.zero_begin), P.zero_end - P.zero_begin, s));
     EVOSORT_LAUNCH("radix_histogram", s,
                    launch_radix_histogram(P.kd, keys_in, n, P.bits, (int)P.info.passes, hist, s));
-    EVOSORT_LAUNCH("radix_scan", s, launch_radix_scan(hist, bases, P.bits, (int)P.info.passes, nullptr, s));
+    EVOSORT_LAUNCH("radix_scan", s,
+                   launch_radix_scan(hist, bases, P.bits, (int)P.info.passes, nullptr, nullptr, nullptr, s));
     RadixPassArgs a{};
     a.keys_in = keys_in;
     a.keys_out = keys_out;
@@ -1212,7 +1217,7 @@ evosort_status evosort_radix_pass(int dtype, const void* keys_in, void* keys_out
     a.shift = pass * (uint32_t)P.bits;
     a.bases = bases + (size_t)pass * bins;
     a.status = at(temp, P.off_status);
-    a.tile_counter = reinterpret_cast<uint32_t*>(at(temp, P.off_ctr));
+    a.ticket = reinterpret_cast<unsigned long long*>(at(temp, P.off_ctr));  // zeroed: no route code
     a.error_word = reinterpret_cast<uint32_t*>(at(temp, P.off_err));
     a.host_error = device_error_word(s);
     a.flags = (P.debug_flags & EVOSORT_DEBUG_WITHHOLD_TILE0) ? RADIX_FLAG_WITHHOLD_T0 : 0u;

@@ -128,6 +128,14 @@ __device__ __forceinline__ uint32_t materialize(uint32_t x)
     return x;
 }
 
+// Makes a uniform value (a kernel argument) present in scalar registers at
+// this point: its load is issued early instead of at its first use.
+template <typename T>
+__device__ __forceinline__ void in_sgprs(T x)
+{
+    asm volatile("" ::"s"(x));
+}
+
 // base[idx] for a 32-bit index: the byte offset is formed in 32 bits, so the
 // load takes one offset register and a base held in scalar registers instead
 // of a 64-bit address per element.  Requires idx * sizeof(T) < 2^32.

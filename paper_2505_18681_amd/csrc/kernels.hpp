@@ -38,15 +38,29 @@ hipError_t launch_tile_prefix(void* counts, int status_bytes, uint32_t tiles, ui
 constexpr uint32_t kTilePrefixBlock = 64;  // tiles per workgroup of the prefix kernels
 
 // Exclusive prefix sums of each pass's 2^bits histogram row.  With `live`
-// (passes words) it also records, per pass, 1 if the pass's digit takes more
-// than one value over the keys and 0 if every key has the same digit there
-// (such a pass would leave the order unchanged).
+// (one word, zero before the launch) it also sets bit p when pass p's digit
+// takes more than one value over the keys; a pass whose digit is the same for
+// every key would leave the order unchanged.
+// `done` (one zeroed word) and `tickets` (passes 64-bit ticket counters,
+// zeroed) go with `live`: the last scan workgroup writes each pass's route
+// code (route_code below) into the upper half of that pass's ticket counter.
 hipError_t launch_radix_scan(const uint64_t* hist, uint64_t* bases, int bits, int passes, uint32_t* live,
-                             hipStream_t s);
+                             uint32_t* done, unsigned long long* tickets, hipStream_t s);
+
+// Route code of a pass in the upper half of its ticket counter: routed, live,
+// its index j among the live passes and their number m.
+constexpr uint32_t kRouteOn = 1u;
+constexpr uint32_t kRouteLive = 2u;
+__host__ __device__ constexpr uint32_t route_code(uint32_t live, uint32_t j, uint32_t m)
+{
+    return kRouteOn | (live ? kRouteLive : 0u) | (j << 8) | (m << 16);
+}
+__host__ __device__ constexpr uint32_t route_j(uint32_t code) { return (code >> 8) & 0xffu; }
+__host__ __device__ constexpr uint32_t route_m(uint32_t code) { return (code >> 16) & 0xffu; }
 
 // Buffers of a whole radix sort, from which each pass picks its input and
 // output on the device once the live passes are known (the scan's `live`
-// words): the launch sequence stays the same whatever digits are constant.
+// word): the launch sequence stays the same whatever digits are constant.
 // Live pass j (0-based among the m live passes) reads what live pass j - 1
 // wrote (the input for j = 0) and writes
 //   keys-only / pairs:  the output when m - 1 - j is even, else the
@@ -60,7 +74,7 @@ hipError_t launch_radix_scan(const uint64_t* hist, uint64_t* bases, int bits, in
 // With no live pass the finishing launch copies the input to the output
 // (argsort: writes the identity permutation).
 struct RadixRoute {
-    const uint32_t* live;  // null: no routing, the pass reads and writes the RadixPassArgs buffers
+    const uint32_t* live;  // the scan's live-pass word (read by the finishing launch); null: no routing
     uint32_t pass, passes;
     uint32_t flags;        // ROUTE_*
     const void* keys_in;
@@ -83,13 +97,14 @@ struct RadixPassArgs {
     uint32_t shift;          // bit offset of this pass's digit in the order word
     const uint64_t* bases;   // 2^bits first output slots of each digit
     void* status;            // tiles * 2^bits look-back words (zeroed)
-    uint32_t* tile_counter;  // zeroed
+    uint32_t* tile_counter;  // zeroed (segmented pass)
+    unsigned long long* ticket;  // radix pass: tile in the lower half, route code in the upper (zeroed: none)
     uint32_t* error_word;    // device error word in the scratch header
     uint32_t* host_error;    // host-visible word also set on a device-side error (may be null)
     uint32_t flags;          // RADIX_FLAG_*
     uint32_t spin_limit;
     uint32_t tiles;          // workgroups launched (= tiles of the pass)
-    RadixRoute route;        // route.live non-null: buffers and IOTA/SKIP_KEYS flags come from the route
+    RadixRoute route;        // used when the ticket carries a route code
 };
 constexpr uint32_t RADIX_FLAG_IOTA = 1u;          // values are the input positions (argsort, first pass)
 constexpr uint32_t RADIX_FLAG_SKIP_KEYS = 2u;     // do not write keys (argsort, last pass)

@@ -157,9 +157,10 @@ hipError_t launch_tile_prefix(void* counts, int status_bytes, uint32_t tiles, ui
 }
 
 hipError_t launch_radix_scan(const uint64_t* hist, uint64_t* bases, int bits, int passes, uint32_t* live,
-                             hipStream_t s)
+                             uint32_t* done, unsigned long long* tickets, hipStream_t s)
 {
-    hipLaunchKernelGGL((radix_scan_kernel<256>), dim3(passes), dim3(256), 0, s, hist, bases, 1 << bits, live);
+    hipLaunchKernelGGL((radix_scan_kernel<256>), dim3(passes), dim3(256), 0, s, hist, bases, 1 << bits, live, done,
+                       tickets);
     return hipGetLastError();
 }
 
@@ -425,9 +426,7 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s)
 // temporary buffer goes to the output; otherwise every workgroup leaves.
 __global__ __launch_bounds__(kStreamThreads) void radix_finish_kernel(RadixRoute r, int64_t n, int kb, int vb)
 {
-    uint32_t m = 0;
-    for (uint32_t q = 0; q < r.passes; ++q)
-        m += r.live[q];
+    const uint32_t m = (uint32_t)__builtin_popcount(*r.live);
     const size_t tid = (size_t)blockIdx.x * kStreamThreads + threadIdx.x;
     const size_t nth = (size_t)gridDim.x * kStreamThreads;
     const bool argsort = (r.flags & ROUTE_ARGSORT) != 0;

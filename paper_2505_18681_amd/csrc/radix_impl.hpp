@@ -335,13 +335,15 @@ __global__ __launch_bounds__(256) void tile_prefix_kernel(ST* __restrict__ count
 
 // ------------------------------------------------------------------------
 // Digit bases: exclusive scan of one histogram row per workgroup; with
-// `live`, whether the row's pass has more than one digit value (a row whose
-// whole count sits in one digit leaves the order unchanged: its pass can go)
+// `live` (one word, zeroed before), bit p set when pass p's digit takes more
+// than one value (a row whose whole count sits in one digit leaves the order
+// unchanged: its pass can go)
 // ------------------------------------------------------------------------
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void radix_scan_kernel(const uint64_t* __restrict__ hist,
                                                              uint64_t* __restrict__ bases, int bins,
-                                                             uint32_t* __restrict__ live)
+                                                             uint32_t* __restrict__ live, uint32_t* done,
+                                                             unsigned long long* tickets)
 {
     __shared__ uint64_t part[THREADS];
     __shared__ uint32_t one_digit;
@@ -375,8 +377,23 @@ __global__ __launch_bounds__(THREADS) void radix_scan_kernel(const uint64_t* __r
                 one_digit = 1;  // every key has this digit
         }
     __syncthreads();
-    if (live && threadIdx.x == 0)
-        live[blockIdx.x] = one_digit ? 0u : 1u;
+    if (!live || threadIdx.x != 0)
+        return;
+    if (!one_digit)
+        atomicOr(live, 1u << blockIdx.x);
+    // The last workgroup to finish writes every pass's route code into the
+    // upper half of its ticket counter, so that a pass learns its route from
+    // the ticket it takes anyway.
+    __threadfence();
+    if (atomicAdd(done, 1u) != gridDim.x - 1)
+        return;
+    __threadfence();
+    const uint32_t mask = __hip_atomic_load(live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t m = (uint32_t)__builtin_popcount(mask);
+    for (uint32_t q = 0; q < gridDim.x; ++q) {
+        const uint32_t j = (uint32_t)__builtin_popcount(mask & ((1u << q) - 1u));
+        tickets[q] = (unsigned long long)route_code((mask >> q) & 1u, j, m) << 32;
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -490,7 +507,7 @@ struct PassLds {
     __attribute__((aligned(16))) unsigned char uni[UNION_BYTES];
     int64_t gofs[BINS];  // output slot of tile position 0, per digit (32-bit values while n < 2^30)
     uint32_t wtot[WAVES];
-    uint32_t ticket;  // the workgroup's tile number, shared from the lane that took it
+    unsigned long long ticket;  // the workgroup's ticket (route code and tile), shared from the lane that took it
 };
 
 // Everything a workgroup does for one tile after it has its tile number.
@@ -786,20 +803,10 @@ __device__ __forceinline__ void pass_tile(const RadixPassArgs& a, const PassIo& 
     }
 }
 
-// A routed pass (see RadixRoute) picks its buffers from the live passes:
-// returns false when its own digit is constant (the whole pass is skipped).
-// The live words are the same for every workgroup and lane.
-__device__ __forceinline__ bool route_pass(const RadixRoute& r, PassIo& io)
+// A routed pass (see RadixRoute) picks its buffers from its route code: live
+// pass j of m live passes.
+__device__ __forceinline__ void route_pass(const RadixRoute& r, uint32_t j, uint32_t m, PassIo& io)
 {
-    uint32_t j = 0, m = 0, me = 0;
-    for (uint32_t q = 0; q < r.passes; ++q) {
-        const uint32_t l = r.live[q];
-        m += l;
-        j += q < r.pass ? l : 0u;
-        me = q == r.pass ? l : me;
-    }
-    if (!me)
-        return false;
     if (r.flags & ROUTE_ARGSORT) {
         const bool to_out = ((m - 1 - j) & 1) == 0;
         io.keys_in = j == 0 ? r.keys_in : (((j - 1) & 1) ? r.keys_tmp2 : r.keys_tmp);
@@ -817,7 +824,6 @@ __device__ __forceinline__ bool route_pass(const RadixRoute& r, PassIo& io)
         io.vals_out = out_now ? r.vals_out : r.vals_tmp;
         io.vals_in = j == 0 ? r.vals_in : (out_before ? r.vals_out : r.vals_tmp);
     }
-    return true;
 }
 
 // One workgroup per tile.  The tile number is a ticket taken from an atomic
@@ -833,14 +839,33 @@ __global__ __launch_bounds__(THREADS) void radix_pass_kernel(RadixPassArgs a, Or
     static_assert((1 << BITS) <= 4096, "digit field is 12 bits");
     __shared__ Lds L;
 
-    PassIo io{a.keys_in, a.keys_out, a.vals_in, a.vals_out, a.flags};
-    if (a.route.live && !route_pass(a.route, io))
-        return;  // uniform: this pass's digit is the same for every key
-
+    // The ticket's lower half is the tile; its upper half is the pass's route
+    // code, which the scan kernel wrote into the counter (0: not routed).
     if (threadIdx.x == 0)
-        L.ticket = atomicAdd(a.tile_counter, 1u);
+        L.ticket = atomicAdd(a.ticket, 1ull);
+    // The route's buffers are kernel arguments: have them in scalar registers
+    // while the ticket is in flight, not requested once it has arrived (the
+    // tile's loads wait on the choice).
+    in_sgprs(a.route.flags);
+    in_sgprs(a.route.keys_in);
+    in_sgprs(a.route.keys_out);
+    in_sgprs(a.route.keys_tmp);
+    if constexpr (VB != 0) {
+        in_sgprs(a.route.keys_tmp2);
+        in_sgprs(a.route.vals_in);
+        in_sgprs(a.route.vals_out);
+        in_sgprs(a.route.vals_tmp);
+    }
     __syncthreads();
-    const uint32_t tile = L.ticket;
+    const unsigned long long t = L.ticket;
+    const uint32_t code = __builtin_amdgcn_readfirstlane((uint32_t)(t >> 32));
+    const uint32_t tile = __builtin_amdgcn_readfirstlane((uint32_t)t);
+    PassIo io{a.keys_in, a.keys_out, a.vals_in, a.vals_out, a.flags};
+    if (code & kRouteOn) {
+        if (!(code & kRouteLive))
+            return;  // uniform: this pass's digit is the same for every key
+        route_pass(a.route, route_j(code), route_m(code), io);
+    }
     if (tile >= a.tiles)
         return;  // uniform across the workgroup
     const int64_t tile_start = (int64_t)tile * TILE;
@@ -877,7 +902,7 @@ __global__ __launch_bounds__(THREADS) void seg_radix_pass_kernel(SegPassArgs sa,
     // The ticket is the same in every lane; saying so (and the same for the
     // segment's fields) keeps the segment's description and pointers in
     // scalar registers.
-    const uint32_t t = __builtin_amdgcn_readfirstlane(L.ticket);
+    const uint32_t t = __builtin_amdgcn_readfirstlane((uint32_t)L.ticket);
     const uint32_t slot = __builtin_amdgcn_readfirstlane(sa.tile_slot[t]);
     SegLarge g = sa.large[slot];
     g.begin = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)g.begin >> 32)) << 32) |

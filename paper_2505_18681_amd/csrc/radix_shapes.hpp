@@ -23,6 +23,18 @@ constexpr size_t radix_lds_bytes(int kb, int vb, int bits, int threads, int item
     return (hist > stage ? hist : stage) + bins * 8 + (size_t)(threads / 64) * 4 + 16;
 }
 
+// Waves per SIMD the pass kernel must keep so that registers do not cost it
+// a workgroup that LDS would allow on a CU (4 SIMDs per CU), at most 6 (80
+// VGPRs, which the pass fits in): the compiler is held to this bound.
+constexpr int radix_pass_waves_per_eu(int kb, int vb, int bits, int threads, int items)
+{
+    const size_t lds = radix_lds_bytes(kb, vb, bits, threads, items);
+    const int groups = lds > 0 ? (int)(kLdsLimit / lds) : 1;
+    const int waves = (groups < 1 ? 1 : groups) * (threads / 64);
+    const int per_eu = (waves + 3) / 4;
+    return per_eu > 6 ? 6 : (per_eu < 1 ? 1 : per_eu);
+}
+
 // Preferred shape per (key bytes, value bytes), measured at 8-bit digits on
 // 1e9-key arrays; compiled at every digit width (used where it fits in LDS).
 // The GA tuner's pick of 16-wave, 16384-key tiles over the earlier 8-wave,
