@@ -657,7 +657,7 @@ def _csv_rows(directory: str, suffix: str):
 
 def short_kernel_name(name: str) -> str:
     """`void evosort::radix_pass_kernel<4, 0, ...>(args)` -> `radix_pass_kernel<4, 0, ...>`."""
-    name = name.strip()
+    name = name.strip().replace("(anonymous namespace)::", "")
     for prefix in ("void ",):
         if name.startswith(prefix):
             name = name[len(prefix):]
@@ -769,8 +769,36 @@ def summarize_pmc(fetch_dir: str, write_dir: str, kernel: str, bytes_per_launch:
     return "\n".join(lines) + "\n"
 
 
+def summarize_counters(dirs: list, kernels: list, commands: list, title: str) -> str:
+    """Markdown table of hardware counters (rocprofv3 --pmc runs, any counters): per kernel whose short name
+    starts with one of `kernels`, the mean value per dispatch of every counter collected."""
+    table, order = {}, []
+    for d in dirs:
+        for r in _csv_rows(d, "counter_collection.csv"):
+            k = short_kernel_name(r["Kernel_Name"])
+            if not any(k.startswith(x) for x in kernels):
+                continue
+            c = r["Counter_Name"]
+            per = table.setdefault(k, {}).setdefault(c, {})
+            per[int(r["Dispatch_Id"])] = per.get(int(r["Dispatch_Id"]), 0.0) + float(r["Counter_Value"])
+            if c not in order:
+                order.append(c)
+    lines = [f"# {title}", "", "Counter runs (one rocprofv3 --pmc run per group of counters):", "", "```"] + commands
+    lines += ["```", "", "Mean value per dispatch (summed over the device's units):", "",
+              "| kernel | dispatches | " + " | ".join(order) + " |", "|---|---|" + "---|" * len(order)]
+    for k in sorted(table):
+        vals = table[k]
+        nd = max(len(v) for v in vals.values())
+        cells = []
+        for c in order:
+            v = vals.get(c)
+            cells.append(f"{sum(v.values()) / len(v):.4g}" if v else "")
+        lines.append(f"| `{k}` | {nd} | " + " | ".join(cells) + " |")
+    return "\n".join(lines) + "\n"
+
+
 def main():
-    if len(sys.argv) > 1 and sys.argv[1] in ("--summarize-trace", "--summarize-pmc"):
+    if len(sys.argv) > 1 and sys.argv[1] in ("--summarize-trace", "--summarize-pmc", "--summarize-counters"):
         return summarize_main()
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -954,6 +982,7 @@ def summarize_main():
     ap = argparse.ArgumentParser(description="Summarize rocprofv3 CSV output of this script as markdown")
     ap.add_argument("--summarize-trace", metavar="DIR")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR")
     ap.add_argument("--kernel", default="radix_pass_kernel<4, 0, 8, 768, 24")
     ap.add_argument("--skip", type=int, default=0, help="leading launches of the kernel to leave out (warm-up)")
     ap.add_argument("--passes", type=int, default=4)
@@ -964,7 +993,9 @@ def summarize_main():
     ap.add_argument("--command", action="append", default=[], help="command line that produced the CSVs")
     ap.add_argument("--title", default="")
     a = ap.parse_args()
-    if a.summarize_trace:
+    if a.summarize_counters:
+        print(summarize_counters(a.summarize_counters, a.kernel.split(";"), a.command, a.title), end="")
+    elif a.summarize_trace:
         print(summarize_trace(a.summarize_trace, a.kernel, a.skip, a.passes, a.bytes_per_launch,
                               "\n".join(a.command), a.title), end="")
     else:

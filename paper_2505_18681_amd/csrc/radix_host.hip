@@ -102,10 +102,16 @@ hipError_t launch_radix_histogram_tiles(const KeyDesc& kd, const void* keys, int
         return hipSuccess;
     const int copies = kHistThreads / kWave;
     const size_t lds = ((size_t)copies * passes + 1) * 256 * 4;
-    // Workgroups stride over the tiles; 16384 of them (about 3 tiles each at
-    // 1e9 int32 keys) beat 4096 and 8192 (1e9 int32: 1.06 ms against 1.10 and
-    // 1.07) despite four times the global flushes of 4096.
-    const uint32_t grid = tiles < 16384 ? tiles : 16384;
+    // Workgroups stride over the tiles, about three tiles each, between 2048
+    // and 16384 workgroups: every workgroup flushes its counts with global
+    // atomics, so fewer of them flush less, while 16384 keep the largest
+    // arrays' reads in flight (int32 keys: 1e9 1.06 ms with 16384 against
+    // 1.10 and 1.07 with 4096 and 8192; 1e8 0.158 ms with 2048 against 0.181
+    // with one workgroup per tile).  The kernel is bound by the throughput
+    // of its LDS atomics: 4 per 4-byte key, one per digit position.
+    const uint32_t third = tiles / 3;
+    const uint32_t want = third < 2048 ? 2048 : (third > 16384 ? 16384 : third);
+    const uint32_t grid = tiles < want ? tiles : want;
     auto* h = reinterpret_cast<unsigned long long*>(hist);
 #define EVOSORT_HT(KB, P, ST, U)                                                                                 \
     do {                                                                                                       \
