@@ -299,6 +299,57 @@ def run_tuned_bench(es, torch, n: int, seed: int, pop: int, generations: int, re
             "entries": out, "search_s": round(time.perf_counter() - t0, 1)}
 
 
+def run_auto_table_bench(es, torch, seed: int, steps: int = 7):
+    """Where the GA table the library compiles in replaces the hand-coded defaults of the automatic choice
+    (A_code 0), the sort with the table's pick (default params), with the hand-coded default (A_code 4) and
+    with the closed-form parameters, on uniform keys at each row's size class; median of `steps` event-timed
+    sorts after a quarter second of untimed ones, outputs checked identical."""
+    import numpy as np
+
+    import workloads
+    from paper_2505_18681_amd import tuner
+
+    stream = torch.cuda.current_stream()
+
+    def median_ms(keys, out, p):
+        temp = torch.empty(max(es.temp_bytes(es.OP_SORT, es.dtype_code(keys.dtype), keys.numel(), 0, p), 256),
+                           dtype=torch.uint8, device="cuda")
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 0.25:
+            es.sort(keys, params=p, out=out, temp=temp)
+            torch.cuda.synchronize()
+        ts = []
+        for _ in range(steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            es.sort(keys, params=p, out=out, temp=temp)
+            b.record(stream)
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    entries = []
+    for kb, n, algo, th, it in tuner.auto_table_rows(tuner.packaged_table()):
+        for name in [d for d, b in tuner.KEY_BYTES.items() if b == kb and d in ("int32", "float32", "int64")]:
+            keys = torch.from_numpy(workloads.uniform(np.dtype(name), n, seed)).cuda()
+            outs = [torch.empty_like(keys) for _ in range(3)]
+            cases = (("table", es.default_params()), ("hand_coded", es.default_params(algo=es.ALGO_RADIX)),
+                     ("closed_form", tuner.closed_form_params(es, name, n)))
+            res = {"dtype": name, "n": n}
+            for (label, p), out in zip(cases, outs):
+                info = es.plan(es.OP_SORT, es.dtype_code(keys.dtype), n, 0, p)
+                res[label + "_ms"] = round(median_ms(keys, out, p), 4)
+                res[label + "_tile"] = [info["block_threads"], info["items_per_thread"]]
+            if not (torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])):
+                raise RuntimeError("table, hand-coded and closed-form sorts differ")
+            res["table_speedup"] = round(res["hand_coded_ms"] / res["table_ms"], 3)
+            entries.append(res)
+            del keys, outs
+            torch.cuda.empty_cache()
+    return {"workload": "uniform keys at every size class where the compiled GA table overrides the automatic "
+                        "choice's hand-coded defaults", "entries": entries}
+
+
 def serving_trace(count: int, rate: float, seed: int, lo: float = 1e3, hi: float = 1e8):
     """Request trace: Poisson arrivals at `rate` per second, log-uniform sizes in [lo, hi], dtype uniform over
     int32, int64, float32; returns (arrival seconds, sizes, dtype names)."""
@@ -887,6 +938,9 @@ def main():
                                     per_array=not args.batched_no_per_array)
         print(f"# batched: {batched['ms']}", file=sys.stderr, flush=True)
 
+    auto_table = run_auto_table_bench(es, torch, args.seed)
+    print(f"# auto table: {auto_table['entries']}", file=sys.stderr, flush=True)
+
     tuned = None
     if not args.no_tuned:
         tuned = run_tuned_bench(es, torch, args.tuned_n, args.seed, args.tuned_pop, args.tuned_generations, 3)
@@ -972,6 +1026,7 @@ def main():
         "routines": routines,
         "batched": batched,
         "tuned": tuned,
+        "auto_table": auto_table,
         "serving": serving,
         "paper_sweep": paper_sweep,
     }

@@ -16,6 +16,9 @@
 #include "radix_shapes.hpp"
 #include "segmented.hpp"
 #include "small_sort.hpp"
+#include "tuned_table.hpp"
+
+#include <math.h>
 
 using namespace evosort;
 
@@ -312,6 +315,21 @@ void default_params(evosort_params* p)
 
 enum ForcePath { FORCE_NONE = 0, FORCE_RADIX = 1, FORCE_MERGE = 2 };
 
+// The GA table's row for a keys-only sort of n keys of key_bytes (the row of
+// that key width whose size class is within half a decade of n), or null.
+const TunedRow* tuned_row(int key_bytes, int64_t n)
+{
+    if (n < 2)
+        return nullptr;
+    const double x = log10((double)n);
+    for (int i = 0; i < kTunedRowCount; ++i) {
+        const TunedRow& r = kTunedRows[i];
+        if (r.key_bytes == key_bytes && fabs(x - log10((double)r.n)) < 0.5)
+            return &r;
+    }
+    return nullptr;
+}
+
 evosort_status make_plan(int op, int dtype, int64_t n, uint32_t value_bytes, const evosort_params* pin, Plan* P,
                          ForcePath force = FORCE_NONE)
 {
@@ -352,6 +370,20 @@ evosort_status make_plan(int op, int dtype, int64_t n, uint32_t value_bytes, con
     P->t_ins = p.insertion_threshold;
     P->shape = p.block_threads ? RadixShape{(int)p.block_threads, (int)p.items_per_thread}
                                : radix_default_shape_for(kb, vb, (int)p.digit_bits, n);
+    // Automatic choice (A_code 0) of a keys-only sort with no shape given:
+    // where the GA tuner's table has a row for this key width and size class,
+    // its routine and tile replace the hand-coded defaults (Sec. 4.2,
+    // Algorithm 2; the table is compiled in from the tuner's output).
+    int tuned_algo = 0;
+    if (p.algo == EVOSORT_ALGO_AUTO && op == EVOSORT_OP_SORT && !p.block_threads) {
+        const TunedRow* row = tuned_row(kb, n);
+        const int status_bytes = n < kStatus32Limit && !(p.debug_flags & EVOSORT_DEBUG_WIDE_STATUS) ? 4 : 8;
+        if (row && radix_pass_available(kb, vb, (int)p.digit_bits, RadixShape{row->threads, row->items},
+                                        status_bytes)) {
+            P->shape = RadixShape{row->threads, row->items};
+            tuned_algo = row->algo;
+        }
+    }
     const int64_t cap = small_sort_capacity(kb, vb);
     P->info.small_capacity = (uint64_t)cap;
     P->info.digit_bits = p.digit_bits;
@@ -361,7 +393,8 @@ evosort_status make_plan(int op, int dtype, int64_t n, uint32_t value_bytes, con
     // The adaptive partition sort (Sec. 4.3, Algorithm 6), with the readings
     // of the GPU library: the small-array branch is capped by one
     // workgroup's capacity; float keys take the radix branch too; A_code 0
-    // means radix.
+    // means radix unless the tuner's table picked the mergesort for this size
+    // class.
     int path;
     if (force == FORCE_RADIX)
         path = EVOSORT_PATH_RADIX;
@@ -371,7 +404,7 @@ evosort_status make_plan(int op, int dtype, int64_t n, uint32_t value_bytes, con
         path = EVOSORT_PATH_COPY;
     else if ((uint64_t)n < p.fallback_threshold && n <= cap)
         path = EVOSORT_PATH_SMALL;
-    else if (p.algo == EVOSORT_ALGO_MERGE)
+    else if (p.algo == EVOSORT_ALGO_MERGE || tuned_algo == EVOSORT_ALGO_MERGE)
         path = EVOSORT_PATH_MERGE;
     else
         path = EVOSORT_PATH_RADIX;

@@ -500,9 +500,160 @@ def tuned_params(es, dtype_name: str, n: int, dist: str = "uniform"):
     return params_for(es, packaged_table(), dtype_name, n, dist)
 
 
+# --------------------------------------------------------------------------
+# Closed forms (Sec. 7, Eq. 1 and Eq. 2) and the table the library compiles in
+# --------------------------------------------------------------------------
+# The paper fits each GA-chosen threshold T(n) by a quadratic in x = log10(n)
+# and clamps it to the GA's bounds.  Its coefficients, as printed:
+PAPER_T_INSERTION = (-106975922 / 731875, 748808234 / 313357, -9314994284 / 997461)
+PAPER_T_NUMPY = (-1173315880 / 833461, 15503630602 / 854233, 3935718871 / 743070)
+
+
+def quadratic(coeffs, n: float) -> float:
+    """a x^2 + b x + c at x = log10(n)."""
+    a, b, c = coeffs
+    x = math.log10(n)
+    return a * x * x + b * x + c
+
+
+def paper_thresholds(n: int) -> Tuple[int, int]:
+    """(T_insertion, T_numpy) of the paper's closed forms (Eq. 1, Eq. 2), rounded and clamped to the GA's
+    bounds [2, 2048] and [1000, 100000]."""
+    t_ins = min(max(int(round(quadratic(PAPER_T_INSERTION, n))), 2), 2048)
+    t_np = min(max(int(round(quadratic(PAPER_T_NUMPY, n))), 1000), 100000)
+    return t_ins, t_np
+
+
+KEY_BYTES = {"int32": 4, "uint32": 4, "float32": 4, "int64": 8, "float64": 8}
+DTYPE_CODES = {"int32": 1, "int64": 2, "uint32": 3, "float32": 4, "float64": 5}
+
+
+def effective_tile(es, dtype_name: str, n: int, params) -> int:
+    """Keys per radix tile a keys-only sort of n keys with `params` uses (0 if it takes another routine)."""
+    info = es.plan(es.OP_SORT, DTYPE_CODES[dtype_name], n, 0, params)
+    return int(info["tile_keys"]) if info["path_name"] == "radix" else 0
+
+
+def fit_tile_formula(es, table: dict, key_bytes: int) -> Tuple[float, float, float]:
+    """The Eq. 1 / Eq. 2 form refit on the GPU table: least-squares quadratic in x = log10(n) of log2(keys per
+    radix tile) over the GA's picks for uniform keys of this width (every size class whose pick is the
+    radix routine, hand-coded shapes resolved for the digit width and n the pick was made at)."""
+    xs, ys = [], []
+    for e in table.get("entries", []):
+        if e.get("dist") != "uniform" or KEY_BYTES.get(e.get("dtype")) != key_bytes:
+            continue
+        d = dict(e["params"])
+        d["shape"] = tuple(d.get("shape", (0, 0)))
+        tile = effective_tile(es, e["dtype"], int(e["n"]), to_params(es, d))
+        if tile:
+            xs.append(math.log10(e["n"]))
+            ys.append(math.log2(tile))
+    a, b, c = np.polyfit(np.array(xs), np.array(ys), 2)
+    return float(a), float(b), float(c)
+
+
+# Coefficients of that fit on the packaged table (tests refit them from the
+# table): log2(keys per tile) = a x^2 + b x + c, x = log10(n).
+GPU_TILE_FORMULA = {4: (-0.2027, 3.3880, 0.0889), 8: (0.0425, -0.1013, 11.3529)}
+
+# Largest tile the radix pass compiles for keys only at 8-bit digits.
+_MAX_TILE = {4: 768 * 24, 8: 768 * 12}
+
+
+def closed_form_params(es, dtype_name: str, n: int):
+    """Library params from the GPU closed form: the compiled tile shape (at 8-bit digits, keys only) whose
+    key count is nearest, on a log scale, to 2^(a x^2 + b x + c), at most the largest default tile."""
+    kb = KEY_BYTES[dtype_name]
+    want = min(2.0 ** quadratic(GPU_TILE_FORMULA[kb], n), _MAX_TILE[kb])
+    best, best_d = None, None
+    for shape in RADIX_SHAPES[1:]:
+        p = to_params(es, {"algo": 4, "digit_bits": 8, "shape": shape})
+        try:
+            es.plan(es.OP_SORT, DTYPE_CODES[dtype_name], max(n, 2), 0, p)
+        except es.EvosortError:
+            continue
+        d = abs(math.log2(shape[0] * shape[1]) - math.log2(want))
+        if best is None or d < best_d - 1e-9 or (abs(d - best_d) <= 1e-9 and shape[0] > best[0]):
+            best, best_d = shape, d
+    return to_params(es, {"algo": 4, "digit_bits": 8, "shape": best})
+
+
+# A table entry overrides the hand-coded default tile only where the GA's
+# re-timed pick beat the re-timed default by this much (smaller gains are
+# within the timing noise of one tuning run).
+AUTO_MIN_GAIN = 0.02
+
+
+def auto_table_rows(table: dict):
+    """Rows of the table the library compiles in for EVOSORT_ALGO_AUTO: (key bytes, size class n, A_code,
+    threads, keys per thread), one per (key width, size class) whose uniform-key pick beats the default by
+    AUTO_MIN_GAIN for every key type of that width that has an entry; equal picks only."""
+    picks = {}
+    for e in table.get("entries", []):
+        if e.get("dist") != "uniform" or e["dtype"] not in KEY_BYTES:
+            continue
+        gain = 1.0 - e["ms"] / e["default_ms"] if e.get("default_ms") else 0.0
+        d = e["params"]
+        shape = tuple(d.get("shape", (0, 0)))
+        pick = (int(d["algo"]), shape[0], shape[1]) if gain >= AUTO_MIN_GAIN and shape != (0, 0) or (
+            gain >= AUTO_MIN_GAIN and int(d["algo"]) == 3) else None
+        picks.setdefault((KEY_BYTES[e["dtype"]], int(e["n"])), []).append(pick)
+    rows = []
+    for (kb, n), ps in sorted(picks.items()):
+        if ps and all(p is not None and p == ps[0] for p in ps):
+            rows.append((kb, n) + ps[0])
+    return rows
+
+
+def emit_header(table: dict) -> str:
+    """C++ header with auto_table_rows(table), the table the library compiles in."""
+    lines = [
+        "// Size classes where the GA tuner's pick replaces the hand-coded defaults of",
+        "// EVOSORT_ALGO_AUTO for keys-only sorts (Sec. 4.2, Algorithm 2, run on an",
+        "// MI355X): key bytes, size class (keys), A_code, tile threads, keys per thread.",
+        "// A row applies to arrays within half a decade of its size class.  Written by",
+        "// `python -m paper_2505_18681_amd.tuner --emit-header` from the packaged",
+        "// table tuned/mi355x.json; do not edit.",
+        "#pragma once",
+        "",
+        "#include <stdint.h>",
+        "",
+        "namespace evosort {",
+        "",
+        "struct TunedRow {",
+        "    int key_bytes;",
+        "    int64_t n;",
+        "    int algo;",
+        "    int threads;",
+        "    int items;",
+        "};",
+        "",
+        "constexpr TunedRow kTunedRows[] = {",
+    ]
+    rows = auto_table_rows(table)
+    for kb, n, algo, th, it in rows:
+        lines.append(f"    {{{kb}, {n}, {algo}, {th}, {it}}},")
+    if not rows:
+        lines.append("    {0, 0, 0, 0, 0},")
+    lines += ["};", f"constexpr int kTunedRowCount = {len(rows)};", "", "}  // namespace evosort", ""]
+    return "\n".join(lines)
+
+
+HEADER_PATH = __import__("os").path.join(__import__("os").path.dirname(__import__("os").path.abspath(__file__)),
+                                         "csrc", "tuned_table.hpp")
+
+
 def main(argv=None):
     """Tune the sort per key type, size class and distribution (and optionally a batch) on the current GPU and
     write a JSON table."""
+    import sys as _sys
+
+    args_in = list(_sys.argv[1:] if argv is None else argv)
+    if args_in[:1] == ["--emit-header"]:
+        with open(HEADER_PATH, "w") as f:
+            f.write(emit_header(packaged_table()))
+        print(HEADER_PATH)
+        return
     import argparse
     import os
     import sys

@@ -59,3 +59,28 @@ def test_tuned_segmented_matches_oracle():
     p = tuner.to_params(es, d)
     got = to_np(es.segmented_sort(to_dev(keys), to_dev(offs), params=p))
     assert_bits_equal(got, oracle.segmented_sort(keys, offs), f"tuned segmented {entry['params']}")
+
+
+@pytest.mark.parametrize("wide", [0, 1])
+@pytest.mark.parametrize("dt", [np.int32, np.float32])
+def test_auto_table_and_closed_form_sorts_match_oracle(dt, wide):
+    """The table's row (1e7 4-byte keys: its own tile) taken by EVOSORT_ALGO_AUTO, and the closed-form
+    parameters, sort element by element like the oracle; ragged size inside the row's size class."""
+    es = require_gpu()
+    from paper_2505_18681_amd import tuner
+
+    rows = [r for r in tuner.auto_table_rows(tuner.packaged_table()) if r[0] == 4]
+    assert rows
+    n = rows[0][1] + 12_347
+    keys = workloads.float_mix(dt, n, 3) if dt == np.float32 else workloads.uniform(dt, n, 3)
+    keys[::11] = keys[5]
+    want = oracle.sort(keys)
+    k = to_dev(keys)
+    auto = es.default_params(debug_flags=es.DEBUG_WIDE_STATUS if wide else 0)
+    info = es.plan(es.OP_SORT, es.dtype_code(k.dtype), n, 0, auto)
+    assert (info["block_threads"], info["items_per_thread"]) == rows[0][3:]
+    assert info["status_bytes"] == (8 if wide else 4)
+    assert_bits_equal(to_np(es.sort(k, params=auto, check=True)), want, "auto (table row)")
+    name = np.dtype(dt).name
+    p = tuner.closed_form_params(es, name, n)
+    assert_bits_equal(to_np(es.sort(k, params=p, check=True)), want, "closed form")

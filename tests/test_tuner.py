@@ -159,3 +159,92 @@ def test_params_for_picks_the_nearest_size_class():
     p = tuner.params_for(es, table, "int64", 10 ** 8)
     d = es.default_params()
     assert (p.algo, p.digit_bits) == (d.algo, d.digit_bits)
+
+
+# --------------------------------------------------------------------------
+# Closed forms (Sec. 7, Eq. 1 and Eq. 2) and the table the library compiles in
+# --------------------------------------------------------------------------
+def test_paper_closed_forms_match_worked_values(golden):
+    from paper_2505_18681_amd import tuner
+
+    rows = golden("paper_closed_form.txt")
+    assert len(rows) == 4
+    for n, t_ins, t_np in rows:
+        assert tuner.paper_thresholds(int(n)) == (int(t_ins), int(t_np)), n
+
+
+def test_paper_closed_forms_have_the_stated_extrema():
+    """Sec. 7 states the extrema x* = -b / (2a): about 8.17 for T_insertion and 6.45 for T_numpy."""
+    from paper_2505_18681_amd import tuner
+
+    for coeffs, x_star in ((tuner.PAPER_T_INSERTION, 8.17), (tuner.PAPER_T_NUMPY, 6.45)):
+        a, b, _ = coeffs
+        assert a < 0 and abs(-b / (2 * a) - x_star) < 0.01
+
+
+def test_gpu_tile_formula_refits_from_the_table():
+    """The committed coefficients are the least-squares fit over the packaged GA table."""
+    es = pytest.importorskip("paper_2505_18681_amd")
+    from paper_2505_18681_amd import tuner
+
+    table = tuner.packaged_table()
+    for kb in (4, 8):
+        fit = tuner.fit_tile_formula(es, table, kb)
+        assert all(abs(f - c) < 1e-3 for f, c in zip(fit, tuner.GPU_TILE_FORMULA[kb])), (kb, fit)
+
+
+def test_gpu_tile_formula_tracks_the_tables_picks():
+    """At every size class the GA tuned with the radix routine, the closed form's tile is within a factor of
+    two of the GA's pick (shapes exist only in steps)."""
+    import math
+
+    es = pytest.importorskip("paper_2505_18681_amd")
+    from paper_2505_18681_amd import tuner
+
+    checked = 0
+    for e in tuner.packaged_table()["entries"]:
+        if e["dist"] != "uniform":
+            continue
+        d = dict(e["params"])
+        d["shape"] = tuple(d["shape"])
+        pick = tuner.effective_tile(es, e["dtype"], e["n"], tuner.to_params(es, d))
+        if not pick:
+            continue
+        form = tuner.effective_tile(es, e["dtype"], e["n"], tuner.closed_form_params(es, e["dtype"], e["n"]))
+        assert abs(math.log2(form) - math.log2(pick)) <= 1.0, (e["dtype"], e["n"], form, pick)
+        checked += 1
+    assert checked >= 10
+
+
+def test_compiled_table_is_the_packaged_one():
+    """csrc/tuned_table.hpp is what the emitter writes for the packaged GA table."""
+    from paper_2505_18681_amd import tuner
+
+    with open(tuner.HEADER_PATH) as f:
+        assert f.read() == tuner.emit_header(tuner.packaged_table())
+
+
+def test_auto_dispatch_follows_the_table():
+    """EVOSORT_ALGO_AUTO of a keys-only sort takes the table's tile within half a decade of a row's size
+    class; explicit A_code 4, a given shape, pairs and argsort keep the hand-coded defaults."""
+    es = pytest.importorskip("paper_2505_18681_amd")
+    from paper_2505_18681_amd import tuner
+
+    rows = tuner.auto_table_rows(tuner.packaged_table())
+    assert rows, "the packaged table has rows"
+    codes = {4: es.INT32, 8: es.INT64}
+    for kb, n, algo, th, it in rows:
+        for m in (n, int(n * 3.1), int(n / 3.1)):
+            info = es.plan(es.OP_SORT, codes[kb], m)
+            assert (info["block_threads"], info["items_per_thread"]) == (th, it), (kb, m)
+            assert info["path_name"] == ("merge" if algo == 3 else "radix")
+            radix = es.plan(es.OP_SORT, codes[kb], m, 0, es.default_params(algo=es.ALGO_RADIX))
+            assert (radix["block_threads"], radix["items_per_thread"]) != (th, it)
+            pairs = es.plan(es.OP_SORT_PAIRS, codes[kb], m, 4)
+            pairs_radix = es.plan(es.OP_SORT_PAIRS, codes[kb], m, 4, es.default_params(algo=es.ALGO_RADIX))
+            assert (pairs["block_threads"], pairs["items_per_thread"]) == (pairs_radix["block_threads"],
+                                                                           pairs_radix["items_per_thread"])
+            given = es.plan(es.OP_SORT, codes[kb], m, 0, es.default_params(block_threads=512, items_per_thread=16))
+            assert (given["block_threads"], given["items_per_thread"]) == (512, 16)
+        far = es.plan(es.OP_SORT, codes[kb], int(n * 3.3))
+        assert (far["block_threads"], far["items_per_thread"]) != (th, it)
