@@ -245,12 +245,30 @@ __global__ __launch_bounds__(kBlockSortThreads) void merge_block_sort_kernel(Mer
     const U* keys_in = reinterpret_cast<const U*>(a.keys_in);
 
     // Load the block.  Values are parked in LDS now, so that writing them
-    // back over vals_in (in place) cannot race with reading them.
-    for (int i = threadIdx.x; i < nb; i += kBlockSortThreads) {
-        buf[0][pad16(i)] = R::make(om.to_order(keys_in[start + i]), (uint32_t)i);
-        if constexpr (VB != 0) {
-            const V* vals_in = reinterpret_cast<const V*>(a.vals_in);
-            vpark[i] = a.iota ? (V)(start + i) : vals_in[start + i];
+    // back over vals_in (in place) cannot race with reading them.  A thread's
+    // loads are all issued before any of them is waited for.
+    constexpr int LOADS = CAP / kBlockSortThreads;
+    {
+        U kr[LOADS];
+        V vr[VB ? LOADS : 1];
+        const V* vals_in = reinterpret_cast<const V*>(a.vals_in);
+#pragma unroll
+        for (int q = 0; q < LOADS; ++q) {
+            const int i = threadIdx.x + q * kBlockSortThreads;
+            if (i < nb) {
+                kr[q] = keys_in[start + i];
+                if constexpr (VB != 0)
+                    vr[q] = a.iota ? (V)(start + i) : vals_in[start + i];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < LOADS; ++q) {
+            const int i = threadIdx.x + q * kBlockSortThreads;
+            if (i < nb) {
+                buf[0][pad16(i)] = R::make(om.to_order(kr[q]), (uint32_t)i);
+                if constexpr (VB != 0)
+                    vpark[i] = vr[q];
+            }
         }
     }
     __syncthreads();
@@ -401,14 +419,32 @@ __global__ __launch_bounds__(kRoundThreads) void merge_round_kernel(MergeRoundAr
     const int ca = (int)(a1 - a0), cb = (int)(b1 - b0);
     const int cnt = ca + cb;
 
-    // the tile's A slice, then its B slice
+    // the tile's A slice, then its B slice; a thread's loads are all issued
+    // before any of them is waited for
     const U* keys_in = reinterpret_cast<const U*>(a.keys_in);
     const V* vals_in = reinterpret_cast<const V*>(a.vals_in);
-    for (int i = threadIdx.x; i < cnt; i += kRoundThreads) {
-        const int64_t src = i < ca ? s + a0 + i : s + na + b0 + (i - ca);
-        s_in[pad16(i)] = om.to_order(keys_in[src]);
-        if constexpr (VB != 0)
-            v_in[i] = vals_in[src];
+    {
+        U kr[PER];
+        V vr[VB ? PER : 1];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = threadIdx.x + q * kRoundThreads;
+            if (i < cnt) {
+                const int64_t src = i < ca ? s + a0 + i : s + na + b0 + (i - ca);
+                kr[q] = keys_in[src];
+                if constexpr (VB != 0)
+                    vr[q] = vals_in[src];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = threadIdx.x + q * kRoundThreads;
+            if (i < cnt) {
+                s_in[pad16(i)] = om.to_order(kr[q]);
+                if constexpr (VB != 0)
+                    v_in[i] = vr[q];
+            }
+        }
     }
     __syncthreads();
     {
@@ -436,12 +472,16 @@ __global__ __launch_bounds__(kRoundThreads) void merge_round_kernel(MergeRoundAr
     __syncthreads();
     U* keys_out = reinterpret_cast<U*>(a.keys_out);
     V* vals_out = reinterpret_cast<V*>(a.vals_out);
-    for (int i = threadIdx.x; i < cnt; i += kRoundThreads) {
-        const int64_t dst = s + k0 + i;
-        if (!a.skip_keys)
-            keys_out[dst] = om.from_order(s_out[pad16(i)]);
-        if constexpr (VB != 0)
-            vals_out[dst] = v_out[pad16(i)];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = threadIdx.x + q * kRoundThreads;
+        if (i < cnt) {
+            const int64_t dst = s + k0 + i;
+            if (!a.skip_keys)
+                keys_out[dst] = om.from_order(s_out[pad16(i)]);
+            if constexpr (VB != 0)
+                vals_out[dst] = v_out[pad16(i)];
+        }
     }
 }
 
