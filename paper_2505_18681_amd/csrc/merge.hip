@@ -273,23 +273,58 @@ __global__ __launch_bounds__(kBlockSortThreads) void merge_block_sort_kernel(Mer
     }
     __syncthreads();
 
-    // Chunks of t_ins: place each record at (chunk start + number of smaller
-    // records in its chunk).
-    for (int i = threadIdx.x; i < nb; i += kBlockSortThreads) {
-        const int c0 = (i / t_ins) * t_ins;
-        const int c1 = c0 + t_ins < nb ? c0 + t_ins : nb;
-        const W r = buf[0][pad16(i)];
-        int rank = 0;
-        for (int j = c0; j < c1; ++j)
-            rank += R::before(buf[0][pad16(j)], j, r, i) ? 1 : 0;
-        buf[1][pad16(c0 + rank)] = r;
+    constexpr int PER = CAP / kBlockSortThreads;
+    if (t_ins == PER && nb == CAP) {
+        // Chunks of exactly one thread's PER records (a full block): the
+        // thread puts its chunk in order in registers with a bitonic sorting
+        // network.  Records compare by (word, position) -- positions are
+        // distinct, or with bare words equal records are identical -- so the
+        // network's order is the stable order insertion sort gives.
+        W x[PER];
+        const int c0 = threadIdx.x * PER;
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            x[q] = buf[0][pad16(c0 + q)];
+#pragma unroll
+        for (int size = 2; size <= PER; size *= 2) {
+#pragma unroll
+            for (int st = size / 2; st >= 1; st /= 2) {
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    const int pq = q ^ st;
+                    if (pq > q) {
+                        const bool up = (q & size) == 0;
+                        const bool sw = up ? R::before(x[pq], c0 + pq, x[q], c0 + q)
+                                           : R::before(x[q], c0 + q, x[pq], c0 + pq);
+                        const W lo = sw ? x[pq] : x[q];
+                        const W hi = sw ? x[q] : x[pq];
+                        x[q] = lo;
+                        x[pq] = hi;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            buf[1][pad16(c0 + q)] = x[q];
+    } else {
+        // Chunks of t_ins: place each record at (chunk start + number of
+        // smaller records in its chunk).
+        for (int i = threadIdx.x; i < nb; i += kBlockSortThreads) {
+            const int c0 = (i / t_ins) * t_ins;
+            const int c1 = c0 + t_ins < nb ? c0 + t_ins : nb;
+            const W r = buf[0][pad16(i)];
+            int rank = 0;
+            for (int j = c0; j < c1; ++j)
+                rank += R::before(buf[0][pad16(j)], j, r, i) ? 1 : 0;
+            buf[1][pad16(c0 + rank)] = r;
+        }
     }
     __syncthreads();
 
     // Pairwise merges inside the block, run length doubling from t_ins; on
     // equal records the left run's goes first.  Thread t owns outputs
     // [t*PER, (t+1)*PER) of every level.
-    constexpr int PER = CAP / kBlockSortThreads;
     const auto less = [](const W& x, const W& y) { return R::less(x, y); };
     int cur = 1;
     for (int L = t_ins; L < nb; L *= 2) {
