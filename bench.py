@@ -51,6 +51,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "Gkeys/s and HBM GB/s vs peak, int32/int64 1e9 sort; batched segs/s, p99 latency"
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "radix_pass_int32_1e9_pmc.md")
 KERNEL_SOURCES = ["paper_2505_18681_amd/csrc/radix_impl.hpp", "paper_2505_18681_amd/csrc/common.hpp",
+                  "paper_2505_18681_amd/csrc/kernels.hpp",
                   "paper_2505_18681_amd/csrc/radix_shapes.hpp"]
 
 
@@ -871,6 +872,8 @@ def main():
     ap.add_argument("--batched-no-per-array", action="store_true",
                     help="skip the one-sort-per-array comparison (100k sorts; slow under a kernel trace)")
     ap.add_argument("--no-tuned", action="store_true")
+    ap.add_argument("--no-auto-table", action="store_true",
+                    help="skip the comparison of the compiled GA table with the hand-coded defaults")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-paper-sweep", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
@@ -938,8 +941,10 @@ def main():
                                     per_array=not args.batched_no_per_array)
         print(f"# batched: {batched['ms']}", file=sys.stderr, flush=True)
 
-    auto_table = run_auto_table_bench(es, torch, args.seed)
-    print(f"# auto table: {auto_table['entries']}", file=sys.stderr, flush=True)
+    auto_table = None
+    if not args.no_auto_table:
+        auto_table = run_auto_table_bench(es, torch, args.seed)
+        print(f"# auto table: {auto_table['entries']}", file=sys.stderr, flush=True)
 
     tuned = None
     if not args.no_tuned:
