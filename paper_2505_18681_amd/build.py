@@ -108,10 +108,23 @@ def _check_pass_kernels(usage: dict):
         raise RuntimeError("radix pass kernels lost occupancy or spill:\n  " + "\n  ".join(bad))
 
 
+def _check_no_scratch(usage: dict, what: str):
+    """No kernel of the unit uses scratch (spills or private arrays in memory)."""
+    bad = [f"{name}: {u['ScratchSize']} bytes of scratch per lane" for name, u in usage.items()
+           if u.get("ScratchSize", 0) > 0]
+    if bad:
+        raise RuntimeError(f"{what} kernels use scratch:\n  " + "\n  ".join(bad))
+
+
+# Units whose kernels' resource usage is checked at build time.
+CHECKED_UNITS = {"radix_inst.hip": _check_pass_kernels,
+                 "merge.hip": lambda usage: _check_no_scratch(usage, "mergesort")}
+
+
 def _compile(unit, verbose, defines=()):
     src, obj, extra = unit
     out = os.path.join(BUILD, obj)
-    report = src == "radix_inst.hip"
+    report = src in CHECKED_UNITS
     cmd = [HIPCC] + COMMON + list(defines) + extra + ["-c", os.path.join(CSRC, src), "-o", out]
     if report:
         cmd.append("-Rpass-analysis=kernel-resource-usage")
@@ -127,7 +140,7 @@ def _compile(unit, verbose, defines=()):
     if msgs and verbose:
         print(msgs, flush=True)
     if report:
-        _check_pass_kernels(_resource_usage(text))
+        CHECKED_UNITS[src](_resource_usage(text))
     return out
 
 

@@ -3,12 +3,18 @@
 // each chunk, then merges pairs of runs while the run length doubles.  Here:
 //
 //   merge_block_sort_kernel  one workgroup per block of T_ins * 2^m keys (as
-//                            many as fit in LDS): every chunk of T_ins keys is
-//                            put in order by rank counting (the parallel form
-//                            of insertion sort: a key's place is the number of
-//                            chunk keys before it in the stable order), then
-//                            the chunks are merged pairwise inside LDS until
-//                            the block is one run;
+//                            many as fit in LDS), 8 keys per thread: every
+//                            chunk of T_ins keys is put in order by rank
+//                            counting (the parallel form of insertion sort: a
+//                            key's place is the number of chunk keys before it
+//                            in the stable order), then the chunks are merged
+//                            pairwise inside LDS until the block is one run.
+//                            A full block with T_ins dividing 8 takes the
+//                            register path instead: each thread sorts its 8
+//                            keys, the wave merges them up to runs of 512 with
+//                            bitonic merges across lanes (DPP and swizzles),
+//                            and each later level is merged in LDS one wave
+//                            per 512 outputs (wave_lds_merge);
 //   merge_partition_kernel   for every output tile of a merge round, a binary
 //                            search along the tile's cross diagonal of the two
 //                            runs (merge path) finds how many outputs come from
@@ -39,7 +45,7 @@ namespace {
 
 constexpr int kPartitionThreads = 256;  // partition kernel
 constexpr int kRoundThreads = 512;      // round kernel
-constexpr int kBlockSortThreads = 512;  // block sort
+constexpr int kBlockPer = 8;            // block sort: records per thread
 
 // LDS index of element p of a padded array: one spare element every 16.
 __device__ __forceinline__ int pad16(int p) { return p + (p >> 4); }
@@ -131,11 +137,51 @@ struct KeyIdx<uint64_t> {
     static __device__ __forceinline__ KeyIdx top() { return {~0ull, 0xffffffffu}; }
 };
 
-// Keys per block-sort workgroup: 4096, or 2048 for 16-byte records.
+// c ? a : b, field by field for the 16-byte records: a select of the whole
+// aggregate can be lowered through private (scratch) memory.
+template <typename T>
+__device__ __forceinline__ T pick(bool c, const T& a, const T& b)
+{
+    return c ? a : b;
+}
+__device__ __forceinline__ Rec<8>::W pick(bool c, const Rec<8>::W& a, const Rec<8>::W& b)
+{
+    return Rec<8>::W{c ? a.ord : b.ord, c ? a.pos : b.pos, 0u};
+}
+__device__ __forceinline__ KeyIdx<uint64_t> pick(bool c, const KeyIdx<uint64_t>& a, const KeyIdx<uint64_t>& b)
+{
+    return KeyIdx<uint64_t>{c ? a.k : b.k, c ? a.i : b.i};
+}
+
+// (a, b) <- (the smaller, the larger) under `less`; records that `less`
+// does not order are identical.  Bare 32-bit words take min and max.
+template <typename W, typename Less>
+__device__ __forceinline__ void order2(W& a, W& b, Less less)
+{
+    const bool sw = less(b, a);
+    const W lo = pick(sw, b, a), hi = pick(sw, a, b);
+    a = lo;
+    b = hi;
+}
+template <typename Less>
+__device__ __forceinline__ void order2(uint32_t& a, uint32_t& b, Less)
+{
+    const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+    a = lo;
+    b = hi;
+}
+
+// Keys per block-sort workgroup: 4096, or 2048 for 16-byte records; the
+// workgroup has one thread per kBlockPer of them.
 template <int KB, int VB>
 constexpr int block_cap()
 {
     return KB == 8 && VB != 0 ? 2048 : 4096;
+}
+template <int KB, int VB>
+constexpr int block_threads()
+{
+    return block_cap<KB, VB>() / kBlockPer;
 }
 
 // Merges the sorted runs A = src[a0, a0 + na) and B = src[b0, b0 + nb)
@@ -163,15 +209,15 @@ __device__ __forceinline__ void merge_run(const T* src, int a0, int na, int b0, 
     for (int o = k; o < k_end; ++o) {
         // branch-free step: emit the smaller head, refill it with one read
         const bool take_a = j >= nb || (i < na && !less(hb, ha));
-        emit(o, take_a ? ha : hb, take_a ? a0 + i : b0 + j);
+        emit(o, pick(take_a, ha, hb), take_a ? a0 + i : b0 + j);
         i += take_a ? 1 : 0;
         j += take_a ? 0 : 1;
         const int next = take_a ? a0 + i : b0 + j;
         const bool more = take_a ? i < na : j < nb;
         const T x = src[pad16(more ? next : a0)];  // a0 is always a valid index
-        const T nx = more ? x : top;
-        ha = take_a ? nx : ha;
-        hb = take_a ? hb : nx;
+        const T nx = pick(more, x, top);
+        ha = pick(take_a, nx, ha);
+        hb = pick(take_a, hb, nx);
     }
 }
 
@@ -206,18 +252,14 @@ __device__ __forceinline__ void merge_window(Load load, int a0, int na, int b0, 
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const T v = y[PER - 1 - q];
-        x[q] = less(v, x[q]) ? v : x[q];  // A's element on ties
+        x[q] = pick(less(v, x[q]), v, x[q]);  // A's element on ties
     }
 #pragma unroll
     for (int st = PER / 2; st >= 1; st >>= 1) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            if ((q & st) == 0) {
-                const T u = x[q], v = x[q + st];
-                const bool sw = less(v, u);
-                x[q] = sw ? v : u;
-                x[q + st] = sw ? u : v;
-            }
+            if ((q & st) == 0)
+                order2(x[q], x[q + st], less);
         }
     }
 #pragma unroll
@@ -226,8 +268,167 @@ __device__ __forceinline__ void merge_window(Load load, int a0, int na, int b0, 
             emit(k + q, x[q]);
 }
 
+// --------------------------------------------------------- wave exchanges --
+// The 32-bit register v of lane (lane ^ M) of the wave.  Masks inside a row
+// of 16 lanes are DPP moves (no LDS pipe); 16 and 31 swizzle inside 32 lanes;
+// 32 and 63 go through ds_bpermute.
+template <int M>
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t v, int lane)
+{
+    const int s = (int)v;
+    if constexpr (M == 1)
+        return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
+    else if constexpr (M == 2)
+        return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+    else if constexpr (M == 3)
+        return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0x1B, 0xF, 0xF, true);  // quad_perm [3,2,1,0]
+    else if constexpr (M == 7)
+        return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0x141, 0xF, 0xF, true);  // row_half_mirror
+    else if constexpr (M == 15)
+        return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0x140, 0xF, 0xF, true);  // row_mirror
+    else if constexpr (M == 8)
+        return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0x128, 0xF, 0xF, true);  // row_ror:8
+    else if constexpr (M == 4)
+        return lane_xor32<3>(lane_xor32<7>(v, lane), lane);  // (l ^ 7) ^ 3
+    else if constexpr (M == 16 || M == 31)
+        return (uint32_t)__builtin_amdgcn_ds_swizzle(s, (M << 10) | 0x1F);  // bit mode: l ^ M in 32 lanes
+    else {
+        static_assert(M == 32 || M == 63, "mask not provided");
+        return (uint32_t)__builtin_amdgcn_ds_bpermute((lane ^ M) << 2, s);
+    }
+}
+
+template <int M>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v, int lane)
+{
+    return lane_xor32<M>(v, lane);
+}
+template <int M>
+__device__ __forceinline__ uint64_t lane_xor(uint64_t v, int lane)
+{
+    const uint32_t lo = lane_xor32<M>((uint32_t)v, lane);
+    const uint32_t hi = lane_xor32<M>((uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+template <int M>
+__device__ __forceinline__ Rec<8>::W lane_xor(const Rec<8>::W& v, int lane)
+{
+    return Rec<8>::W{lane_xor<M>(v.ord, lane), lane_xor32<M>(v.pos, lane), 0u};
+}
+
+// Half-cleaner steps of a bitonic merge across lanes: every register of lane
+// l meets the same register of lane l ^ M, for M = M0, M0 / 2, ..., 1; the
+// lower lane keeps the smaller.
+template <int M, int N, typename W, typename Less>
+__device__ __forceinline__ void half_clean_lanes(W (&x)[N], int lane, Less less)
+{
+    if constexpr (M >= 1) {
+        // the lower lane takes y when it is smaller, the upper when it is not
+        const bool high = (lane & M) != 0;
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const W y = lane_xor<M>(x[q], lane);
+            x[q] = pick(less(y, x[q]) != high, y, x[q]);
+        }
+        half_clean_lanes<M / 2>(x, lane, less);
+    }
+}
+
+// Merge levels of run length L = PER, 2 PER, ..., 32 PER inside one wave,
+// in registers: lane l holds records [l PER, (l + 1) PER) of the wave's
+// 64 PER, each lane's PER in order on entry, all 64 PER in order on exit.  A
+// level pairs runs of L records (L / PER lanes) and merges each pair with a
+// bitonic merge: every record of the left run meets its mirror image in the
+// right run, then half-cleaners at distances L/2 down to 1 sort both halves.
+// Records compare by `less`, under which no two distinct records are equal,
+// so the result is the one unique order the LDS merges would give.
+template <int PER, int L, typename W, typename Less>
+__device__ __forceinline__ void wave_merge_levels(W (&x)[PER], int lane, Less less)
+{
+    if constexpr (L < 64 * PER) {
+        constexpr int G = 2 * L / PER;  // lanes holding one pair of runs
+        const bool high = (lane & (G / 2)) != 0;
+        W y[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            y[q] = lane_xor<G - 1>(x[PER - 1 - q], lane);
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            x[q] = pick(less(y[q], x[q]) != high, y[q], x[q]);
+        half_clean_lanes<L / 2 / PER>(x, lane, less);  // distances L/2 .. PER: across lanes
+#pragma unroll
+        for (int st = PER / 2; st >= 1; st >>= 1) {
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                if ((q & st) == 0)
+                    order2(x[q], x[q + st], less);
+        }
+        wave_merge_levels<PER, 2 * L>(x, lane, less);
+    }
+}
+
+// Number of A elements among the first k outputs of the merge of the sorted
+// runs A = src[a0, a0 + L) and B = src[b0, b0 + L) (merge path, A first on
+// ties), found by the whole wave: each round the 64 lanes test 64 evenly
+// spaced candidates at once and a ballot keeps the interval between the last
+// that passes and the first that fails, so runs of up to 4096 take two
+// rounds.  Wave-uniform arguments; every lane returns the same value.
+template <typename W, typename Less>
+__device__ __forceinline__ int wave_merge_path(const W* src, int a0, int b0, int L, int k, int lane, Less less)
+{
+    int lo = k - L > 0 ? k - L : 0;
+    int hi = k < L ? k : L;
+    while (lo < hi) {
+        const int step = (hi - lo + 63) >> 6;
+        const int c = lo + (lane + 1) * step;
+        // A[c - 1] goes before B[k - c]: at least c outputs come from A
+        const bool pass = c <= hi && !less(src[pad16(b0 + k - c)], src[pad16(a0 + c - 1)]);
+        const int t = __popcll(__ballot(pass));  // the passing lanes are a prefix
+        lo += t * step;
+        hi = hi < lo + step - 1 ? hi : lo + step - 1;
+    }
+    return lo;
+}
+
+// One LDS merge level of a full block, one wave per 64 PER consecutive
+// outputs [o, o + 64 PER) of the merge of the pair of runs of length L that
+// starts at s (L >= 64 PER).  The wave finds where its outputs start and end
+// on both runs (wave_merge_path), loads its A slice ascending followed by its
+// B slice descending -- a bitonic sequence -- lane-striped (element e in
+// register e / 64 of lane e % 64, so consecutive lanes read consecutive LDS
+// words), sorts it with the half-cleaners of a bitonic merge (distances of 64
+// and more inside the lane, below 64 across lanes) and stores it striped.
+template <int PER, typename W, typename Less>
+__device__ __forceinline__ void wave_lds_merge(const W* src, W* dst, int s, int L, int o, int lane, Less less)
+{
+    constexpr int OUT = 64 * PER;
+    const int a0 = s, b0 = s + L;
+    const int k = o - s;
+    const int i0 = wave_merge_path(src, a0, b0, L, k, lane, less);
+    const int i1 = wave_merge_path(src, a0, b0, L, k + OUT, lane, less);
+    const int na = i1 - i0;
+    const int b_last = b0 + (k + OUT - i1) - 1;  // the B slice's last element
+    W x[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = q * 64 + lane;
+        x[q] = src[pad16(e < na ? a0 + i0 + e : b_last - (e - na))];
+    }
+#pragma unroll
+    for (int d = PER / 2; d >= 1; d >>= 1) {  // distances 64 d, inside the lane
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if ((q & d) == 0)
+                order2(x[q], x[q + d], less);
+    }
+    half_clean_lanes<32>(x, lane, less);
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+        dst[pad16(o + q * 64 + lane)] = x[q];
+}
+
 template <int KB, int VB>
-__global__ __launch_bounds__(kBlockSortThreads) void merge_block_sort_kernel(MergeBlockArgs a,
+__global__ __launch_bounds__((block_threads<KB, VB>())) void merge_block_sort_kernel(MergeBlockArgs a,
                                                                              OrderMap<typename KeyWord<KB>::U> om,
                                                                              int t_ins, int block_keys)
 {
@@ -236,6 +437,7 @@ __global__ __launch_bounds__(kBlockSortThreads) void merge_block_sort_kernel(Mer
     using R = BlockRec<KB, VB>;
     using W = typename R::W;
     constexpr int CAP = block_cap<KB, VB>();
+    constexpr int THREADS = block_threads<KB, VB>();
     __shared__ W buf[2][padded16(CAP)];
     __shared__ V vpark[VB ? CAP : 1];
 
@@ -247,14 +449,14 @@ __global__ __launch_bounds__(kBlockSortThreads) void merge_block_sort_kernel(Mer
     // Load the block.  Values are parked in LDS now, so that writing them
     // back over vals_in (in place) cannot race with reading them.  A thread's
     // loads are all issued before any of them is waited for.
-    constexpr int LOADS = CAP / kBlockSortThreads;
+    constexpr int LOADS = CAP / THREADS;
     {
         U kr[LOADS];
         V vr[VB ? LOADS : 1];
         const V* vals_in = reinterpret_cast<const V*>(a.vals_in);
 #pragma unroll
         for (int q = 0; q < LOADS; ++q) {
-            const int i = threadIdx.x + q * kBlockSortThreads;
+            const int i = threadIdx.x + q * THREADS;
             if (i < nb) {
                 kr[q] = keys_in[start + i];
                 if constexpr (VB != 0)
@@ -263,7 +465,7 @@ __global__ __launch_bounds__(kBlockSortThreads) void merge_block_sort_kernel(Mer
         }
 #pragma unroll
         for (int q = 0; q < LOADS; ++q) {
-            const int i = threadIdx.x + q * kBlockSortThreads;
+            const int i = threadIdx.x + q * THREADS;
             if (i < nb) {
                 buf[0][pad16(i)] = R::make(om.to_order(kr[q]), (uint32_t)i);
                 if constexpr (VB != 0)
@@ -273,13 +475,17 @@ __global__ __launch_bounds__(kBlockSortThreads) void merge_block_sort_kernel(Mer
     }
     __syncthreads();
 
-    constexpr int PER = CAP / kBlockSortThreads;
-    if (t_ins == PER && nb == CAP) {
-        // Chunks of exactly one thread's PER records (a full block): the
-        // thread puts its chunk in order in registers with a bitonic sorting
-        // network.  Records compare by (word, position) -- positions are
-        // distinct, or with bare words equal records are identical -- so the
-        // network's order is the stable order insertion sort gives.
+    constexpr int PER = kBlockPer;
+    const auto less = [](const W& x, const W& y) { return R::less(x, y); };
+    int first_lds_run = t_ins;  // run length of the first merge level done in LDS
+    if (PER % t_ins == 0 && nb == CAP) {
+        // A full block whose chunks tile each thread's PER records: the
+        // thread sorts its records in registers with a bitonic sorting
+        // network, which gives what sorting its chunks and merging them up to
+        // runs of PER gives.  Records with values carry distinct positions,
+        // and bare words that compare equal are identical, so the network's
+        // order is the stable one.  The merge levels up to runs of one wave's
+        // 64 PER records follow in registers too.
         W x[PER];
         const int c0 = threadIdx.x * PER;
 #pragma unroll
@@ -293,24 +499,23 @@ __global__ __launch_bounds__(kBlockSortThreads) void merge_block_sort_kernel(Mer
                 for (int q = 0; q < PER; ++q) {
                     const int pq = q ^ st;
                     if (pq > q) {
-                        const bool up = (q & size) == 0;
-                        const bool sw = up ? R::before(x[pq], c0 + pq, x[q], c0 + q)
-                                           : R::before(x[q], c0 + q, x[pq], c0 + pq);
-                        const W lo = sw ? x[pq] : x[q];
-                        const W hi = sw ? x[q] : x[pq];
-                        x[q] = lo;
-                        x[pq] = hi;
+                        if ((q & size) == 0)
+                            order2(x[q], x[pq], less);
+                        else
+                            order2(x[pq], x[q], less);
                     }
                 }
             }
         }
+        wave_merge_levels<PER, PER>(x, (int)(threadIdx.x & (kWave - 1)), less);
+        first_lds_run = kWave * PER;
 #pragma unroll
         for (int q = 0; q < PER; ++q)
             buf[1][pad16(c0 + q)] = x[q];
     } else {
         // Chunks of t_ins: place each record at (chunk start + number of
         // smaller records in its chunk).
-        for (int i = threadIdx.x; i < nb; i += kBlockSortThreads) {
+        for (int i = threadIdx.x; i < nb; i += THREADS) {
             const int c0 = (i / t_ins) * t_ins;
             const int c1 = c0 + t_ins < nb ? c0 + t_ins : nb;
             const W r = buf[0][pad16(i)];
@@ -322,12 +527,22 @@ __global__ __launch_bounds__(kBlockSortThreads) void merge_block_sort_kernel(Mer
     }
     __syncthreads();
 
-    // Pairwise merges inside the block, run length doubling from t_ins; on
-    // equal records the left run's goes first.  Thread t owns outputs
-    // [t*PER, (t+1)*PER) of every level.
-    const auto less = [](const W& x, const W& y) { return R::less(x, y); };
+    // Pairwise merges inside the block, run length doubling from t_ins (or
+    // from the wave's run); on equal records the left run's goes first.
+    // Thread t owns outputs [t*PER, (t+1)*PER) of every level.
     int cur = 1;
-    for (int L = t_ins; L < nb; L *= 2) {
+    if (first_lds_run == kWave * PER) {
+        // the register path's block: full, runs of one wave's records; each
+        // wave merges its share of every level (wave_lds_merge)
+        const int lane = (int)(threadIdx.x & (kWave - 1));
+        const int o = (int)(threadIdx.x / kWave) * kWave * PER;
+        for (int L = first_lds_run; L < CAP; L *= 2) {
+            wave_lds_merge<PER>(buf[cur], buf[cur ^ 1], (o / (2 * L)) * (2 * L), L, o, lane, less);
+            __syncthreads();
+            cur ^= 1;
+        }
+    }
+    for (int L = first_lds_run; L < nb && first_lds_run != kWave * PER; L *= 2) {
         const W* src = buf[cur];
         W* dst = buf[cur ^ 1];
         int o = threadIdx.x * PER;
@@ -357,7 +572,7 @@ __global__ __launch_bounds__(kBlockSortThreads) void merge_block_sort_kernel(Mer
     }
 
     U* keys_out = reinterpret_cast<U*>(a.keys_out);
-    for (int i = threadIdx.x; i < nb; i += kBlockSortThreads) {
+    for (int i = threadIdx.x; i < nb; i += THREADS) {
         const W r = buf[cur][pad16(i)];
         if (!a.skip_keys)
             keys_out[start + i] = om.from_order((U)R::ord(r));
@@ -533,7 +748,7 @@ hipError_t block_sort_t(const KeyDesc& kd, const MergePlan& mp, const MergeBlock
     if (mp.block_keys > (uint64_t)block_cap<KB, VB>() || mp.block_keys == 0)
         return hipErrorInvalidValue;  // a plan made for another value width
     OrderMap<U> om{(U)kd.flip, (U)kd.neg, (U)kd.desc};
-    hipLaunchKernelGGL((merge_block_sort_kernel<KB, VB>), dim3((unsigned)mp.blocks), dim3(kBlockSortThreads), 0, s, a,
+    hipLaunchKernelGGL((merge_block_sort_kernel<KB, VB>), dim3((unsigned)mp.blocks), dim3(block_threads<KB, VB>()), 0, s, a,
                        om, (int)mp.t_ins, (int)mp.block_keys);
     return hipGetLastError();
 }
