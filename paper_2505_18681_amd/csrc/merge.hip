@@ -23,14 +23,15 @@
 //                            slices into LDS, merges them, and writes the tile
 //                            out coalesced.
 //
-// Every merge inside LDS (the block's levels and a round's tile) is split the
-// same way: each thread owns a run of consecutive outputs and finds where its
-// run starts on both inputs by one merge-path search; it then loads that many
-// elements of both inputs from there into registers and keeps the smallest
-// with a bitonic merging network (merge_window), or, where a block level's
-// pairs of runs are not a multiple of the thread's run, merges sequentially
-// with both heads in registers (merge_run).  LDS arrays are padded by one
-// element every 16, so that the threads' runs start in different banks.
+// A round's tile, and the block levels off the register path, are merged in
+// LDS the same way: each thread owns a run of consecutive outputs and finds
+// where its run starts on both inputs by one merge-path search; it then loads
+// that many elements of both inputs from there into registers and keeps the
+// smallest with a bitonic merging network (merge_window), or, where a block
+// level's pairs of runs are not a multiple of the thread's run, merges
+// sequentially with both heads in registers (merge_run).  LDS arrays are
+// padded by one element every 16, so that the threads' runs start in
+// different banks.
 //
 // Stability: with values, block records carry their position, so all records
 // are distinct and every merge is exact; keys-only blocks rank chunk mates by
