@@ -449,7 +449,8 @@ __global__ __launch_bounds__((block_threads<KB, VB>())) void merge_block_sort_ke
 
     // Load the block.  Values are parked in LDS now, so that writing them
     // back over vals_in (in place) cannot race with reading them.  A thread's
-    // loads are all issued before any of them is waited for.
+    // loads are all issued before any of them is waited for: they carry no
+    // branch, a position past the block reads its last key instead.
     constexpr int LOADS = CAP / THREADS;
     {
         U kr[LOADS];
@@ -457,12 +458,11 @@ __global__ __launch_bounds__((block_threads<KB, VB>())) void merge_block_sort_ke
         const V* vals_in = reinterpret_cast<const V*>(a.vals_in);
 #pragma unroll
         for (int q = 0; q < LOADS; ++q) {
-            const int i = threadIdx.x + q * THREADS;
-            if (i < nb) {
-                kr[q] = keys_in[start + i];
-                if constexpr (VB != 0)
-                    vr[q] = a.iota ? (V)(start + i) : vals_in[start + i];
-            }
+            const int i0 = threadIdx.x + q * THREADS;
+            const int i = i0 < nb ? i0 : nb - 1;
+            kr[q] = keys_in[start + i];
+            if constexpr (VB != 0)
+                vr[q] = a.iota ? (V)(start + i) : vals_in[start + i];
         }
 #pragma unroll
         for (int q = 0; q < LOADS; ++q) {
@@ -670,22 +670,24 @@ __global__ __launch_bounds__(kRoundThreads) void merge_round_kernel(MergeRoundAr
     const int ca = (int)(a1 - a0), cb = (int)(b1 - b0);
     const int cnt = ca + cb;
 
-    // the tile's A slice, then its B slice; a thread's loads are all issued
-    // before any of them is waited for
+    // the tile's A slice, then its B slice (element i of the tile is
+    // a_base[i] or b_base[i]); a thread's loads are all issued before any of
+    // them is waited for: they carry no branch, a position past the tile
+    // reads the tile's last element instead (cnt >= 1 here)
     const U* keys_in = reinterpret_cast<const U*>(a.keys_in);
     const V* vals_in = reinterpret_cast<const V*>(a.vals_in);
+    const int64_t a_base = s + a0, b_base = s + na + b0 - ca;
     {
         U kr[PER];
         V vr[VB ? PER : 1];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int i = threadIdx.x + q * kRoundThreads;
-            if (i < cnt) {
-                const int64_t src = i < ca ? s + a0 + i : s + na + b0 + (i - ca);
-                kr[q] = keys_in[src];
-                if constexpr (VB != 0)
-                    vr[q] = vals_in[src];
-            }
+            const int i0 = threadIdx.x + q * kRoundThreads;
+            const int i = i0 < cnt ? i0 : cnt - 1;
+            const int64_t src = (i < ca ? a_base : b_base) + i;
+            kr[q] = keys_in[src];
+            if constexpr (VB != 0)
+                vr[q] = vals_in[src];
         }
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
