@@ -339,7 +339,7 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s)
 // ceilings the radix pass (read and write once) and the histogram (read
 // once) are measured against.
 constexpr int kStreamThreads = 256;
-constexpr int kStreamUnroll = 4;
+constexpr int kStreamUnroll = 8;  // 16-byte words in flight per thread in the streaming kernels
 
 uint32_t stream_grid(size_t bytes)
 {
@@ -362,14 +362,22 @@ __device__ __forceinline__ void copy_range(unsigned char* __restrict__ dst, cons
         uint4* d = reinterpret_cast<uint4*>(dst);
         const uint4* s = reinterpret_cast<const uint4*>(src);
         size_t i = tid;
-        for (; i + (kStreamUnroll - 1) * nthreads < n16; i += kStreamUnroll * nthreads) {
-            uint4 w[kStreamUnroll];
-#pragma unroll
-            for (int u = 0; u < kStreamUnroll; ++u)
-                w[u] = s[i + u * nthreads];
-#pragma unroll
-            for (int u = 0; u < kStreamUnroll; ++u)
-                d[i + u * nthreads] = w[u];
+        // eight 16-byte words in flight per thread
+        for (; i + 7 * nthreads < n16; i += 8 * nthreads) {
+            const uint4 w0 = s[i], w1 = s[i + nthreads], w2 = s[i + 2 * nthreads], w3 = s[i + 3 * nthreads];
+            const uint4 w4 = s[i + 4 * nthreads], w5 = s[i + 5 * nthreads], w6 = s[i + 6 * nthreads],
+                        w7 = s[i + 7 * nthreads];
+            // every load is issued before the first store: the scheduler
+            // would otherwise pair each load with its store and wait on each
+            __builtin_amdgcn_sched_barrier(0);
+            d[i] = w0;
+            d[i + nthreads] = w1;
+            d[i + 2 * nthreads] = w2;
+            d[i + 3 * nthreads] = w3;
+            d[i + 4 * nthreads] = w4;
+            d[i + 5 * nthreads] = w5;
+            d[i + 6 * nthreads] = w6;
+            d[i + 7 * nthreads] = w7;
         }
         for (; i < n16; i += nthreads)
             d[i] = s[i];
