@@ -275,6 +275,10 @@ __global__ __launch_bounds__(THREADS) void radix_histogram8_tiles_kernel(
 // thread per digit), in three steps over blocks of kTilePrefixBlock tiles:
 // block sums, an exclusive scan of the block sums per digit, and the
 // in-place rewrite of each block's counts into prefixes.
+// Tiles whose counts one thread has in flight at once in the prefix kernels.
+constexpr uint32_t kTilePrefixBatch = 16;
+static_assert(kTilePrefixBlock % kTilePrefixBatch == 0, "whole batches per block");
+
 template <typename ST>
 __global__ __launch_bounds__(256) void tile_block_sum_kernel(const ST* __restrict__ counts, uint32_t tiles,
                                                             uint64_t* __restrict__ block_sums)
@@ -282,8 +286,15 @@ __global__ __launch_bounds__(256) void tile_block_sum_kernel(const ST* __restric
     const uint32_t t0 = blockIdx.x * kTilePrefixBlock;
     const uint32_t t1 = t0 + kTilePrefixBlock < tiles ? t0 + kTilePrefixBlock : tiles;
     uint64_t s = 0;
-    for (uint32_t t = t0; t < t1; ++t)
-        s += (uint64_t)counts[(size_t)t * 256 + threadIdx.x];
+    for (uint32_t tb = t0; tb < t1; tb += kTilePrefixBatch) {
+        ST c[kTilePrefixBatch];
+#pragma unroll
+        for (uint32_t j = 0; j < kTilePrefixBatch; ++j)
+            c[j] = counts[(size_t)(tb + j < t1 ? tb + j : t1 - 1) * 256 + threadIdx.x];  // no branch
+#pragma unroll
+        for (uint32_t j = 0; j < kTilePrefixBatch; ++j)
+            s += tb + j < t1 ? (uint64_t)c[j] : 0;
+    }
     block_sums[(size_t)blockIdx.x * 256 + threadIdx.x] = s;
 }
 
@@ -325,11 +336,18 @@ __global__ __launch_bounds__(256) void tile_prefix_kernel(ST* __restrict__ count
     const uint32_t t0 = blockIdx.x * kTilePrefixBlock;
     const uint32_t t1 = t0 + kTilePrefixBlock < tiles ? t0 + kTilePrefixBlock : tiles;
     uint64_t run = block_sums[(size_t)blockIdx.x * 256 + threadIdx.x];
-    for (uint32_t t = t0; t < t1; ++t) {
-        ST* p = &counts[(size_t)t * 256 + threadIdx.x];
-        const uint64_t c = (uint64_t)*p;
-        *p = (ST)run;
-        run += c;
+    for (uint32_t tb = t0; tb < t1; tb += kTilePrefixBatch) {
+        ST c[kTilePrefixBatch];
+#pragma unroll
+        for (uint32_t j = 0; j < kTilePrefixBatch; ++j)
+            c[j] = counts[(size_t)(tb + j < t1 ? tb + j : t1 - 1) * 256 + threadIdx.x];  // no branch
+#pragma unroll
+        for (uint32_t j = 0; j < kTilePrefixBatch; ++j) {
+            if (tb + j < t1) {
+                counts[(size_t)(tb + j) * 256 + threadIdx.x] = (ST)run;
+                run += (uint64_t)c[j];
+            }
+        }
     }
 }
 
