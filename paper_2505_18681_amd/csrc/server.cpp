@@ -106,7 +106,8 @@ struct GatherItem {
 };
 
 // One workgroup per request; every key is 4 or 8 bytes and every pointer
-// and offset is a multiple of 4, so 4-byte words are copied.
+// and offset is a multiple of 4, so 4-byte words are copied, eight in flight
+// per thread (all loads issued before the first store).
 __global__ __launch_bounds__(256) void gather_kernel(const GatherItem* __restrict__ items,
                                                      unsigned char* __restrict__ dst)
 {
@@ -114,7 +115,22 @@ __global__ __launch_bounds__(256) void gather_kernel(const GatherItem* __restric
     const uint32_t* s = reinterpret_cast<const uint32_t*>(it.src);
     uint32_t* d = reinterpret_cast<uint32_t*>(dst + it.dst_off);
     const uint64_t words = it.bytes / 4;
-    for (uint64_t i = threadIdx.x; i < words; i += blockDim.x)
+    const uint64_t bd = blockDim.x;
+    uint64_t i = threadIdx.x;
+    for (; i + 7 * bd < words; i += 8 * bd) {
+        const uint32_t w0 = s[i], w1 = s[i + bd], w2 = s[i + 2 * bd], w3 = s[i + 3 * bd];
+        const uint32_t w4 = s[i + 4 * bd], w5 = s[i + 5 * bd], w6 = s[i + 6 * bd], w7 = s[i + 7 * bd];
+        __builtin_amdgcn_sched_barrier(0);
+        d[i] = w0;
+        d[i + bd] = w1;
+        d[i + 2 * bd] = w2;
+        d[i + 3 * bd] = w3;
+        d[i + 4 * bd] = w4;
+        d[i + 5 * bd] = w5;
+        d[i + 6 * bd] = w6;
+        d[i + 7 * bd] = w7;
+    }
+    for (; i < words; i += bd)
         d[i] = s[i];
 }
 
