@@ -333,7 +333,7 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s)
 }
 
 // ---------------------------------------------------------------- streams --
-// Streaming copy and read: every byte moved once, 16-byte accesses with four
+// Streaming copy and read: every byte moved once, 16-byte accesses with eight
 // of them in flight per thread, a grid-stride loop over the range.  The copy
 // is the library's device-to-device copy; both are also the practical
 // ceilings the radix pass (read and write once) and the histogram (read
