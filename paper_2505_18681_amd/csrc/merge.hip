@@ -44,7 +44,7 @@ namespace evosort {
 
 namespace {
 
-constexpr int kPartitionThreads = 256;  // partition kernel
+constexpr int kPartitionThreads = 64;   // partition kernel: one wave per workgroup, spread over every CU
 constexpr int kRoundThreads = 512;      // round kernel
 constexpr int kBlockPer = 8;            // block sort: records per thread
 
