@@ -330,23 +330,28 @@ def run_auto_table_bench(es, torch, seed: int, steps: int = 7):
         return float(np.median(ts))
 
     entries = []
-    for kb, n, algo, th, it in tuner.auto_table_rows(tuner.packaged_table()):
-        for name in [d for d, b in tuner.KEY_BYTES.items() if b == kb and d in ("int32", "float32", "int64")]:
-            keys = torch.from_numpy(workloads.uniform(np.dtype(name), n, seed)).cuda()
-            outs = [torch.empty_like(keys) for _ in range(3)]
-            cases = (("table", es.default_params()), ("hand_coded", es.default_params(algo=es.ALGO_RADIX)),
-                     ("closed_form", tuner.closed_form_params(es, name, n)))
-            res = {"dtype": name, "n": n}
-            for (label, p), out in zip(cases, outs):
-                info = es.plan(es.OP_SORT, es.dtype_code(keys.dtype), n, 0, p)
-                res[label + "_ms"] = round(median_ms(keys, out, p), 4)
-                res[label + "_tile"] = [info["block_threads"], info["items_per_thread"]]
-            if not (torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])):
-                raise RuntimeError("table, hand-coded and closed-form sorts differ")
-            res["table_speedup"] = round(res["hand_coded_ms"] / res["table_ms"], 3)
-            entries.append(res)
-            del keys, outs
-            torch.cuda.empty_cache()
+    for name, n, _lo, _hi, _algo, _th, _it in tuner.auto_table_rows(tuner.packaged_table()):
+        host = workloads.uniform(np.dtype(name), n, seed)
+        if name == "uint32":
+            keys = torch.from_numpy(host.view(np.int32)).cuda().view(torch.uint32)
+        else:
+            keys = torch.from_numpy(host).cuda()
+        outs = [torch.empty_like(keys) for _ in range(3)]
+        cases = (("table", es.default_params()), ("hand_coded", es.default_params(algo=es.ALGO_RADIX)),
+                 ("closed_form", tuner.closed_form_params(es, name, n)))
+        res = {"dtype": name, "n": n}
+        for (label, p), out in zip(cases, outs):
+            info = es.plan(es.OP_SORT, es.dtype_code(keys.dtype), n, 0, p)
+            res[label + "_ms"] = round(median_ms(keys, out, p), 4)
+            res[label + "_route"] = (info["path_name"] if info["path_name"] != "radix" else
+                                     [info["block_threads"], info["items_per_thread"]])
+        bits = [o.view(torch.int32 if o.element_size() == 4 else torch.int64) for o in outs]
+        if not (torch.equal(bits[0], bits[1]) and torch.equal(bits[0], bits[2])):
+            raise RuntimeError("table, hand-coded and closed-form sorts differ")
+        res["table_speedup"] = round(res["hand_coded_ms"] / res["table_ms"], 3)
+        entries.append(res)
+        del keys, outs, bits, host
+        torch.cuda.empty_cache()
     return {"workload": "uniform keys at every size class where the compiled GA table overrides the automatic "
                         "choice's hand-coded defaults", "entries": entries}
 

@@ -18,8 +18,6 @@
 #include "small_sort.hpp"
 #include "tuned_table.hpp"
 
-#include <math.h>
-
 using namespace evosort;
 
 namespace {
@@ -315,16 +313,13 @@ void default_params(evosort_params* p)
 
 enum ForcePath { FORCE_NONE = 0, FORCE_RADIX = 1, FORCE_MERGE = 2 };
 
-// The GA table's row for a keys-only sort of n keys of key_bytes (the row of
-// that key width whose size class is within half a decade of n), or null.
-const TunedRow* tuned_row(int key_bytes, int64_t n)
+// The GA table's row for a keys-only sort of n keys of type dtype (the row of
+// that key type whose length range lo <= n < hi holds n), or null.
+const TunedRow* tuned_row(int dtype, int64_t n)
 {
-    if (n < 2)
-        return nullptr;
-    const double x = log10((double)n);
     for (int i = 0; i < kTunedRowCount; ++i) {
         const TunedRow& r = kTunedRows[i];
-        if (r.key_bytes == key_bytes && fabs(x - log10((double)r.n)) < 0.5)
+        if (r.dtype == dtype && n >= r.lo && n < r.hi)
             return &r;
     }
     return nullptr;
@@ -371,15 +366,18 @@ evosort_status make_plan(int op, int dtype, int64_t n, uint32_t value_bytes, con
     P->shape = p.block_threads ? RadixShape{(int)p.block_threads, (int)p.items_per_thread}
                                : radix_default_shape_for(kb, vb, (int)p.digit_bits, n);
     // Automatic choice (A_code 0) of a keys-only sort with no shape given:
-    // where the GA tuner's table has a row for this key width and size class,
-    // its routine and tile replace the hand-coded defaults (Sec. 4.2,
-    // Algorithm 2; the table is compiled in from the tuner's output).
+    // where the GA tuner's table has a row for this key type and length,
+    // its routine (and a radix row's tile) replace the hand-coded defaults
+    // (Sec. 4.2, Algorithm 2; the table is compiled in from the tuner's
+    // output).
     int tuned_algo = 0;
     if (p.algo == EVOSORT_ALGO_AUTO && op == EVOSORT_OP_SORT && !p.block_threads) {
-        const TunedRow* row = tuned_row(kb, n);
+        const TunedRow* row = tuned_row(dtype, n);
         const int status_bytes = n < kStatus32Limit && !(p.debug_flags & EVOSORT_DEBUG_WIDE_STATUS) ? 4 : 8;
-        if (row && radix_pass_available(kb, vb, (int)p.digit_bits, RadixShape{row->threads, row->items},
-                                        status_bytes)) {
+        if (row && row->algo == EVOSORT_ALGO_MERGE) {
+            tuned_algo = row->algo;
+        } else if (row && radix_pass_available(kb, vb, (int)p.digit_bits, RadixShape{row->threads, row->items},
+                                               status_bytes)) {
             P->shape = RadixShape{row->threads, row->items};
             tuned_algo = row->algo;
         }

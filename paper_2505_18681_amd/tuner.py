@@ -393,6 +393,21 @@ class SegmentedFitness:
         return float(np.median(times))
 
 
+# After the search the default and the GA's pick are timed again, alternately,
+# this many times each; the table records the two medians.
+RETIME_ROUNDS = 7
+
+
+def retime_pair(time_a: Callable[[], float], time_b: Callable[[], float], rounds: int = RETIME_ROUNDS):
+    """Medians of `rounds` timings of each of two settings taken alternately (a, b, a, b, ...), so that a drift
+    of the GPU's clocks during the re-timing falls on both alike rather than on whichever went first."""
+    ta, tb = [], []
+    for _ in range(rounds):
+        ta.append(time_a())
+        tb.append(time_b())
+    return float(np.median(ta)), float(np.median(tb))
+
+
 def default_individual(es) -> tuple:
     """The library defaults as a sort_space individual (shape (0, 0) = the default tile shape)."""
     p = es.default_params()
@@ -418,9 +433,8 @@ def tune_sort(es, keys, *, seed: int = 42, pop_size: int = POP_SIZE, generations
     fitness.warm(base)
     res = run_ga(space, fitness, seed=seed, pop_size=pop_size, generations=generations, repair=repair,
                  seed_individuals=[base])
-    # both re-timed after the search, side by side
-    default_ms = fitness._time(to_params(es, space.as_dict(base)))
-    best_ms = fitness._time(to_params(es, space.as_dict(res.best)))
+    p_default, p_best = (to_params(es, space.as_dict(x)) for x in (base, res.best))
+    default_ms, best_ms = retime_pair(lambda: fitness._time(p_default), lambda: fitness._time(p_best))
     return {"n": int(keys.numel()), "params": _jsonable(res.best_dict()), "ms": round(best_ms, 4),
             "default_ms": round(default_ms, 4), "ga_best_ms": round(res.best_fitness, 4),
             "evaluations": res.evaluations, "history": res.history,
@@ -437,8 +451,7 @@ def tune_segmented(es, keys, offsets, *, seed: int = 42, pop_size: int = POP_SIZ
     fitness.warm(base)
     res = run_ga(fitness.space, fitness, seed=seed, pop_size=pop_size, generations=generations,
                  seed_individuals=[base])
-    default_ms = fitness(base)
-    best_ms = fitness(res.best)
+    default_ms, best_ms = retime_pair(lambda: fitness(base), lambda: fitness(res.best))
     return {"n": int(keys.numel()), "nseg": int(offsets.numel() - 1), "params": _jsonable(res.best_dict()),
             "ms": round(best_ms, 4), "default_ms": round(default_ms, 4), "ga_best_ms": round(res.best_fitness, 4),
             "evaluations": res.evaluations, "history": res.history,
@@ -554,7 +567,7 @@ def fit_tile_formula(es, table: dict, key_bytes: int) -> Tuple[float, float, flo
 
 # Coefficients of that fit on the packaged table (tests refit them from the
 # table): log2(keys per tile) = a x^2 + b x + c, x = log10(n).
-GPU_TILE_FORMULA = {4: (-0.2027, 3.3880, 0.0889), 8: (0.0425, -0.1013, 11.3529)}
+GPU_TILE_FORMULA = {4: (-0.0836, 1.7086, 5.8113), 8: (-0.3080, 4.4759, -2.9785)}
 
 # Largest tile the radix pass compiles for keys only at 8-bit digits.
 _MAX_TILE = {4: 768 * 24, 8: 768 * 12}
@@ -584,24 +597,50 @@ def closed_form_params(es, dtype_name: str, n: int):
 AUTO_MIN_GAIN = 0.02
 
 
+def _cut(num: int, den: int = 1) -> int:
+    """Smallest integer m >= 0 with den * m^2 >= num (an exact ceil(sqrt(num / den)))."""
+    m = math.isqrt(num // den)
+    while den * m * m < num:
+        m += 1
+    return m
+
+
 def auto_table_rows(table: dict):
-    """Rows of the table the library compiles in for EVOSORT_ALGO_AUTO: (key bytes, size class n, A_code,
-    threads, keys per thread), one per (key width, size class) whose uniform-key pick beats the default by
-    AUTO_MIN_GAIN for every key type of that width that has an entry; equal picks only."""
-    picks = {}
+    """Rows of the table the library compiles in for EVOSORT_ALGO_AUTO: (key type, size class n, lo, hi,
+    A_code, threads, keys per thread), one per (key type, size class) whose uniform-key pick beat the default by
+    AUTO_MIN_GAIN (every entry of that key type and size class, if the table holds several, with the same pick).
+
+    A radix pick carries its tile shape (a pick of the default shape changes nothing the row could hold, so it
+    gives no row); a mergesort pick has no tile, (3, 0, 0).  A row applies to keys-only sorts of lo <= n < hi
+    keys, where lo and hi are the geometric means of its size class and the neighbouring size classes the table
+    tuned for that key type (half a decade beyond the smallest and the largest)."""
+    picks, classes = {}, {}
     for e in table.get("entries", []):
         if e.get("dist") != "uniform" or e["dtype"] not in KEY_BYTES:
             continue
+        dt, n = e["dtype"], int(e["n"])
+        classes.setdefault(dt, set()).add(n)
         gain = 1.0 - e["ms"] / e["default_ms"] if e.get("default_ms") else 0.0
         d = e["params"]
-        shape = tuple(d.get("shape", (0, 0)))
-        pick = (int(d["algo"]), shape[0], shape[1]) if gain >= AUTO_MIN_GAIN and shape != (0, 0) or (
-            gain >= AUTO_MIN_GAIN and int(d["algo"]) == 3) else None
-        picks.setdefault((KEY_BYTES[e["dtype"]], int(e["n"])), []).append(pick)
+        algo, shape = int(d["algo"]), tuple(d.get("shape", (0, 0)))
+        if gain < AUTO_MIN_GAIN:
+            pick = None
+        elif algo == 3:
+            pick = (3, 0, 0)
+        elif shape != (0, 0):
+            pick = (algo, shape[0], shape[1])
+        else:
+            pick = None
+        picks.setdefault((dt, n), []).append(pick)
     rows = []
-    for (kb, n), ps in sorted(picks.items()):
-        if ps and all(p is not None and p == ps[0] for p in ps):
-            rows.append((kb, n) + ps[0])
+    for (dt, n), ps in sorted(picks.items(), key=lambda kv: (DTYPE_CODES[kv[0][0]], kv[0][1])):
+        if not (ps and all(p is not None and p == ps[0] for p in ps)):
+            continue
+        cs = sorted(classes[dt])
+        i = cs.index(n)
+        lo = _cut(cs[i - 1] * n) if i > 0 else _cut(n * n, 10)
+        hi = _cut(n * cs[i + 1]) if i + 1 < len(cs) else _cut(10 * n * n)
+        rows.append((dt, n, lo, hi) + ps[0])
     return rows
 
 
@@ -610,10 +649,11 @@ def emit_header(table: dict) -> str:
     lines = [
         "// Size classes where the GA tuner's pick replaces the hand-coded defaults of",
         "// EVOSORT_ALGO_AUTO for keys-only sorts (Sec. 4.2, Algorithm 2, run on an",
-        "// MI355X): key bytes, size class (keys), A_code, tile threads, keys per thread.",
-        "// A row applies to arrays within half a decade of its size class.  Written by",
-        "// `python -m paper_2505_18681_amd.tuner --emit-header` from the packaged",
-        "// table tuned/mi355x.json; do not edit.",
+        "// MI355X): key type (EVOSORT_* dtype code), size class (keys), the lengths",
+        "// lo <= n < hi the row applies to (geometric means with the neighbouring",
+        "// tuned size classes), A_code, tile threads, keys per thread (0, 0 for the",
+        "// mergesort).  Written by `python -m paper_2505_18681_amd.tuner",
+        "// --emit-header` from the packaged table tuned/mi355x.json; do not edit.",
         "#pragma once",
         "",
         "#include <stdint.h>",
@@ -621,8 +661,10 @@ def emit_header(table: dict) -> str:
         "namespace evosort {",
         "",
         "struct TunedRow {",
-        "    int key_bytes;",
+        "    int dtype;",
         "    int64_t n;",
+        "    int64_t lo;",
+        "    int64_t hi;",
         "    int algo;",
         "    int threads;",
         "    int items;",
@@ -631,10 +673,10 @@ def emit_header(table: dict) -> str:
         "constexpr TunedRow kTunedRows[] = {",
     ]
     rows = auto_table_rows(table)
-    for kb, n, algo, th, it in rows:
-        lines.append(f"    {{{kb}, {n}, {algo}, {th}, {it}}},")
+    for dt, n, lo, hi, algo, th, it in rows:
+        lines.append(f"    {{{DTYPE_CODES[dt]}, {n}, {lo}, {hi}, {algo}, {th}, {it}}},  // {dt}")
     if not rows:
-        lines.append("    {0, 0, 0, 0, 0},")
+        lines.append("    {0, 0, 0, 0, 0, 0, 0},")
     lines += ["};", f"constexpr int kTunedRowCount = {len(rows)};", "", "}  // namespace evosort", ""]
     return "\n".join(lines)
 

@@ -78,17 +78,25 @@ def test_status_strings():
 
 
 def test_dispatch_matches_oracle_rule():
+    """Algorithm 6 as the oracle states it, with A_code 0 read as the compiled GA table's routine for the key
+    type and length (the mergesort where a row picked it, radix elsewhere)."""
+    from paper_2505_18681_amd import tuner
+
+    merge_rows = [r for r in tuner.auto_table_rows(tuner.packaged_table()) if r[4] == es.ALGO_MERGE]
     for dt_name, code in DTYPES.items():
         integer = dt_name != "float32" and dt_name != "float64"
         for algo in (es.ALGO_AUTO, es.ALGO_MERGE, es.ALGO_RADIX):
             for fb in (0, 1, 2, 100, 5000, 16384, 10**6):
                 p = es.default_params(algo=algo, fallback_threshold=fb)
-                for n in (0, 1, 2, 3, 99, 100, 101, 4999, 5000, 8191, 8192, 8193, 16383, 16384, 10**6):
+                for n in (0, 1, 2, 3, 99, 100, 101, 4999, 5000, 8191, 8192, 8193, 16383, 16384, 50_000, 10**6):
                     info = es.plan(es.OP_SORT, code, n, 0, p)
                     if n <= 1:
                         assert info["path_name"] == "copy"
                         continue
-                    want = oracle.aps_path(n, integer, algo, fb, info["small_capacity"], radix_for_floats=True)
+                    a = algo
+                    if algo == es.ALGO_AUTO and any(r[0] == dt_name and r[2] <= n < r[3] for r in merge_rows):
+                        a = es.ALGO_MERGE
+                    want = oracle.aps_path(n, integer, a, fb, info["small_capacity"], radix_for_floats=True)
                     assert info["path_name"] == want, (dt_name, algo, fb, n)
 
 

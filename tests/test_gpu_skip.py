@@ -68,7 +68,7 @@ def test_skip_patterns(name, desc):
     expect_live = {"none": 0, "byte2": 1, "low16": 2, "bytes0and3": 2, "low24": 3, "zipf": 3, "full32": 4,
                    "int64_low32": 4, "int64_byte5": 1}[name]
     assert len(live) == expect_live, live
-    p = es.default_params(fallback_threshold=0, descending=desc)
+    p = es.default_params(algo=es.ALGO_RADIX, fallback_threshold=0, descending=desc)
     perm = oracle.stable_perm(keys, descending=bool(desc))
     want = keys[perm]
     k = to_dev(keys)

@@ -61,26 +61,50 @@ def test_tuned_segmented_matches_oracle():
     assert_bits_equal(got, oracle.segmented_sort(keys, offs), f"tuned segmented {entry['params']}")
 
 
-@pytest.mark.parametrize("wide", [0, 1])
-@pytest.mark.parametrize("dt", [np.int32, np.float32])
-def test_auto_table_and_closed_form_sorts_match_oracle(dt, wide):
-    """The table's row (1e7 4-byte keys: its own tile) taken by EVOSORT_ALGO_AUTO, and the closed-form
-    parameters, sort element by element like the oracle; ragged size inside the row's size class."""
+def _keys(dt, n):
+    keys = workloads.float_mix(dt, n, 3) if np.dtype(dt).kind == "f" else workloads.uniform(dt, n, 3)
+    keys[::11] = keys[5]
+    return keys
+
+
+@pytest.mark.parametrize("dt", [np.int32, np.uint32, np.float32, np.int64, np.float64])
+def test_auto_table_rows_sort_like_the_oracle(dt):
+    """Every row of the compiled GA table for this key type, taken by EVOSORT_ALGO_AUTO at both ends of its
+    length range and at a ragged length inside it, sorts element by element like the oracle: a mergesort row
+    through the mergesort (lengths the small branch takes first aside), a radix row with its own tile at 4- and
+    8-byte look-back words."""
     es = require_gpu()
     from paper_2505_18681_amd import tuner
 
-    rows = [r for r in tuner.auto_table_rows(tuner.packaged_table()) if r[0] == 4]
-    assert rows
-    n = rows[0][1] + 12_347
-    keys = workloads.float_mix(dt, n, 3) if dt == np.float32 else workloads.uniform(dt, n, 3)
-    keys[::11] = keys[5]
-    want = oracle.sort(keys)
+    all_rows = tuner.auto_table_rows(tuner.packaged_table())
+    assert all_rows, "the packaged table has rows"
+    for _, n, lo, hi, algo, th, it in (r for r in all_rows if r[0] == np.dtype(dt).name):
+        for m in (lo, n + 12_347 if n + 12_347 < hi else n + 7, hi - 1):
+            keys = _keys(dt, m)
+            want = oracle.sort(keys)
+            k = to_dev(keys)
+            for wide in ((0, 1) if algo == 4 else (0,)):
+                auto = es.default_params(debug_flags=es.DEBUG_WIDE_STATUS if wide else 0)
+                info = es.plan(es.OP_SORT, es.dtype_code(k.dtype), m, 0, auto)
+                small = m < auto.fallback_threshold and m <= info["small_capacity"]  # Algorithm 6's first branch
+                assert info["path_name"] == ("small" if small else "merge" if algo == 3 else "radix"), (n, m)
+                if algo == 4:
+                    assert (info["block_threads"], info["items_per_thread"]) == (th, it)
+                    assert info["status_bytes"] == (8 if wide else 4)
+                assert_bits_equal(to_np(es.sort(k, params=auto, check=True)), want,
+                                  f"auto, row at {n}, {m} keys, wide {wide}")
+
+
+@pytest.mark.parametrize("n", [1_000_000 + 4_099, 10_000_000 + 12_347])
+@pytest.mark.parametrize("dt", [np.int32, np.float32, np.int64, np.float64])
+def test_closed_form_sorts_match_oracle(dt, n):
+    """The closed-form parameters (the quadratic refit of the GA's tile picks) sort like the oracle at ragged
+    lengths."""
+    es = require_gpu()
+    from paper_2505_18681_amd import tuner
+
+    keys = _keys(dt, n)
     k = to_dev(keys)
-    auto = es.default_params(debug_flags=es.DEBUG_WIDE_STATUS if wide else 0)
-    info = es.plan(es.OP_SORT, es.dtype_code(k.dtype), n, 0, auto)
-    assert (info["block_threads"], info["items_per_thread"]) == rows[0][3:]
-    assert info["status_bytes"] == (8 if wide else 4)
-    assert_bits_equal(to_np(es.sort(k, params=auto, check=True)), want, "auto (table row)")
-    name = np.dtype(dt).name
-    p = tuner.closed_form_params(es, name, n)
-    assert_bits_equal(to_np(es.sort(k, params=p, check=True)), want, "closed form")
+    p = tuner.closed_form_params(es, np.dtype(dt).name, n)
+    assert es.plan(es.OP_SORT, es.dtype_code(k.dtype), n, 0, p)["path_name"] == "radix"
+    assert_bits_equal(to_np(es.sort(k, params=p, check=True)), oracle.sort(keys), "closed form")
