@@ -49,9 +49,10 @@ hipError_t launch_radix_histogram(const KeyDesc& kd, const void* keys, int64_t n
     // per wave) while they fit.
     const size_t per_pass = ((size_t)1 << bits) * 4;
     if (bits == 8 && (passes == 4 || passes == 8)) {
-        // every pass in one launch, one private copy per wave
+        // every pass in one launch, one set of counters per workgroup (as in
+        // launch_radix_histogram_tiles)
         const int grid = histogram_grid(n);
-        const int copies = kHistThreads / kWave;
+        const int copies = 1;
         const size_t lds = (size_t)copies * passes * per_pass;
         auto* h = reinterpret_cast<unsigned long long*>(hist);
         if (kd.bytes == 4 && passes == 4) {
@@ -100,7 +101,11 @@ hipError_t launch_radix_histogram_tiles(const KeyDesc& kd, const void* keys, int
 {
     if (tiles == 0)
         return hipSuccess;
-    const int copies = kHistThreads / kWave;
+    // One set of counters per workgroup: LDS atomics of different waves on
+    // one counter are separate instructions and do not conflict, and the
+    // smaller footprint lets more workgroups share a CU (one copy per wave:
+    // 1e9 int64 keys 2.32 ms, one per workgroup 2.16 ms; int32 keys equal).
+    const int copies = 1;
     const size_t lds = ((size_t)copies * passes + 1) * 256 * 4;
     // Workgroups stride over the tiles, about three tiles each, between 2048
     // and 16384 workgroups: every workgroup flushes its counts with global
