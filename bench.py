@@ -330,7 +330,7 @@ def run_auto_table_bench(es, torch, seed: int, steps: int = 7):
         return float(np.median(ts))
 
     entries = []
-    for name, n, _lo, _hi, _algo, _th, _it in tuner.auto_table_rows(tuner.packaged_table()):
+    for name, n, _lo, _hi, _algo in tuner.auto_table_rows(tuner.packaged_table()):
         host = workloads.uniform(np.dtype(name), n, seed)
         if name == "uint32":
             keys = torch.from_numpy(host.view(np.int32)).cuda().view(torch.uint32)

@@ -81,9 +81,9 @@ typedef enum evosort_dtype {
  * sort.  0 = automatic: radix (the routine the paper's tuner picked at every
  * size, Sec. 6), except for keys-only sorts with no tile shape given whose key
  * type and length fall in a row of the GA tuner's table compiled into the
- * library (Sec. 4.2, Algorithm 2, run on an MI355X): there the row's routine
- * (the mergesort) or radix tile shape is taken.  Other values are rejected
- * with EVOSORT_ERR_INVALID_ARG. */
+ * library (Sec. 4.2, Algorithm 2, run on an MI355X): there the row's routine,
+ * the mergesort, is taken.  Other values are rejected with
+ * EVOSORT_ERR_INVALID_ARG. */
 typedef enum evosort_algo {
     EVOSORT_ALGO_AUTO = 0,
     EVOSORT_ALGO_MERGE = 3,

@@ -366,21 +366,13 @@ evosort_status make_plan(int op, int dtype, int64_t n, uint32_t value_bytes, con
     P->shape = p.block_threads ? RadixShape{(int)p.block_threads, (int)p.items_per_thread}
                                : radix_default_shape_for(kb, vb, (int)p.digit_bits, n);
     // Automatic choice (A_code 0) of a keys-only sort with no shape given:
-    // where the GA tuner's table has a row for this key type and length,
-    // its routine (and a radix row's tile) replace the hand-coded defaults
-    // (Sec. 4.2, Algorithm 2; the table is compiled in from the tuner's
-    // output).
+    // where the GA tuner's table has a row for this key type and length, the
+    // row's routine replaces the default radix sort (Sec. 4.2, Algorithm 2;
+    // the table is compiled in from the tuner's output).
     int tuned_algo = 0;
     if (p.algo == EVOSORT_ALGO_AUTO && op == EVOSORT_OP_SORT && !p.block_threads) {
-        const TunedRow* row = tuned_row(dtype, n);
-        const int status_bytes = n < kStatus32Limit && !(p.debug_flags & EVOSORT_DEBUG_WIDE_STATUS) ? 4 : 8;
-        if (row && row->algo == EVOSORT_ALGO_MERGE) {
+        if (const TunedRow* row = tuned_row(dtype, n))
             tuned_algo = row->algo;
-        } else if (row && radix_pass_available(kb, vb, (int)p.digit_bits, RadixShape{row->threads, row->items},
-                                               status_bytes)) {
-            P->shape = RadixShape{row->threads, row->items};
-            tuned_algo = row->algo;
-        }
     }
     const int64_t cap = small_sort_capacity(kb, vb);
     P->info.small_capacity = (uint64_t)cap;

@@ -567,7 +567,7 @@ def fit_tile_formula(es, table: dict, key_bytes: int) -> Tuple[float, float, flo
 
 # Coefficients of that fit on the packaged table (tests refit them from the
 # table): log2(keys per tile) = a x^2 + b x + c, x = log10(n).
-GPU_TILE_FORMULA = {4: (-0.0836, 1.7086, 5.8113), 8: (-0.3080, 4.4759, -2.9785)}
+GPU_TILE_FORMULA = {4: (-0.0989, 1.9419, 5.0076), 8: (-0.3014, 4.4195, -2.9973)}
 
 # Largest tile the radix pass compiles for keys only at 8-bit digits.
 _MAX_TILE = {4: 768 * 24, 8: 768 * 12}
@@ -606,14 +606,16 @@ def _cut(num: int, den: int = 1) -> int:
 
 
 def auto_table_rows(table: dict):
-    """Rows of the table the library compiles in for EVOSORT_ALGO_AUTO: (key type, size class n, lo, hi,
-    A_code, threads, keys per thread), one per (key type, size class) whose uniform-key pick beat the default by
+    """Rows of the table the library compiles in for EVOSORT_ALGO_AUTO: (key type, size class n, lo, hi, A_code),
+    one per (key type, size class) whose uniform-key pick is the mergesort and beat the default radix sort by
     AUTO_MIN_GAIN (every entry of that key type and size class, if the table holds several, with the same pick).
 
-    A radix pick carries its tile shape (a pick of the default shape changes nothing the row could hold, so it
-    gives no row); a mergesort pick has no tile, (3, 0, 0).  A row applies to keys-only sorts of lo <= n < hi
-    keys, where lo and hi are the geometric means of its size class and the neighbouring size classes the table
-    tuned for that key type (half a decade beyond the smallest and the largest)."""
+    A row applies to keys-only sorts of lo <= n < hi keys, where lo and hi are the geometric means of its size
+    class and the neighbouring size classes the table tuned for that key type (half a decade beyond the smallest
+    and the largest).  The GA's radix tile picks give no row: timed at the ends of such ranges they lost up to
+    9 % to the hand-coded tiles (their gain at the size class itself comes from where that particular n falls
+    against the number of workgroups the GPU holds at once, which moves with n), while the routine picks held
+    over their whole ranges."""
     picks, classes = {}, {}
     for e in table.get("entries", []):
         if e.get("dist") != "uniform" or e["dtype"] not in KEY_BYTES:
@@ -621,17 +623,8 @@ def auto_table_rows(table: dict):
         dt, n = e["dtype"], int(e["n"])
         classes.setdefault(dt, set()).add(n)
         gain = 1.0 - e["ms"] / e["default_ms"] if e.get("default_ms") else 0.0
-        d = e["params"]
-        algo, shape = int(d["algo"]), tuple(d.get("shape", (0, 0)))
-        if gain < AUTO_MIN_GAIN:
-            pick = None
-        elif algo == 3:
-            pick = (3, 0, 0)
-        elif shape != (0, 0):
-            pick = (algo, shape[0], shape[1])
-        else:
-            pick = None
-        picks.setdefault((dt, n), []).append(pick)
+        merge = int(e["params"]["algo"]) == 3
+        picks.setdefault((dt, n), []).append(3 if merge and gain >= AUTO_MIN_GAIN else None)
     rows = []
     for (dt, n), ps in sorted(picks.items(), key=lambda kv: (DTYPE_CODES[kv[0][0]], kv[0][1])):
         if not (ps and all(p is not None and p == ps[0] for p in ps)):
@@ -640,20 +633,20 @@ def auto_table_rows(table: dict):
         i = cs.index(n)
         lo = _cut(cs[i - 1] * n) if i > 0 else _cut(n * n, 10)
         hi = _cut(n * cs[i + 1]) if i + 1 < len(cs) else _cut(10 * n * n)
-        rows.append((dt, n, lo, hi) + ps[0])
+        rows.append((dt, n, lo, hi, ps[0]))
     return rows
 
 
 def emit_header(table: dict) -> str:
     """C++ header with auto_table_rows(table), the table the library compiles in."""
     lines = [
-        "// Size classes where the GA tuner's pick replaces the hand-coded defaults of",
-        "// EVOSORT_ALGO_AUTO for keys-only sorts (Sec. 4.2, Algorithm 2, run on an",
+        "// Size classes where the GA tuner picked the mergesort over the radix sort",
+        "// for EVOSORT_ALGO_AUTO keys-only sorts (Sec. 4.2, Algorithm 2, run on an",
         "// MI355X): key type (EVOSORT_* dtype code), size class (keys), the lengths",
         "// lo <= n < hi the row applies to (geometric means with the neighbouring",
-        "// tuned size classes), A_code, tile threads, keys per thread (0, 0 for the",
-        "// mergesort).  Written by `python -m paper_2505_18681_amd.tuner",
-        "// --emit-header` from the packaged table tuned/mi355x.json; do not edit.",
+        "// tuned size classes), A_code.  Written by `python -m",
+        "// paper_2505_18681_amd.tuner --emit-header` from the packaged table",
+        "// tuned/mi355x.json; do not edit.",
         "#pragma once",
         "",
         "#include <stdint.h>",
@@ -666,17 +659,15 @@ def emit_header(table: dict) -> str:
         "    int64_t lo;",
         "    int64_t hi;",
         "    int algo;",
-        "    int threads;",
-        "    int items;",
         "};",
         "",
         "constexpr TunedRow kTunedRows[] = {",
     ]
     rows = auto_table_rows(table)
-    for dt, n, lo, hi, algo, th, it in rows:
-        lines.append(f"    {{{DTYPE_CODES[dt]}, {n}, {lo}, {hi}, {algo}, {th}, {it}}},  // {dt}")
+    for dt, n, lo, hi, algo in rows:
+        lines.append(f"    {{{DTYPE_CODES[dt]}, {n}, {lo}, {hi}, {algo}}},  // {dt}")
     if not rows:
-        lines.append("    {0, 0, 0, 0, 0, 0, 0},")
+        lines.append("    {0, 0, 0, 0, 0},")
     lines += ["};", f"constexpr int kTunedRowCount = {len(rows)};", "", "}  // namespace evosort", ""]
     return "\n".join(lines)
 

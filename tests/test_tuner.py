@@ -225,53 +225,37 @@ def test_compiled_table_is_the_packaged_one():
 
 
 def test_auto_dispatch_follows_the_table():
-    """EVOSORT_ALGO_AUTO of a keys-only sort takes a row's routine (and a radix row's tile) for every length in
-    the row's range and nowhere outside it; explicit A_code 4, a given shape, pairs and argsort keep the
-    hand-coded defaults."""
+    """EVOSORT_ALGO_AUTO of a keys-only sort takes a row's routine (the mergesort) for every length in the row's
+    range and nowhere outside it; explicit A_code 4, a given shape, pairs and argsort keep the radix sort."""
     es = pytest.importorskip("paper_2505_18681_amd")
     from paper_2505_18681_amd import tuner
 
     rows = tuner.auto_table_rows(tuner.packaged_table())
     assert rows, "the packaged table has rows"
-    for dt, n, lo, hi, algo, th, it in rows:
-        assert lo <= n < hi
+    for dt, n, lo, hi, algo in rows:
+        assert lo <= n < hi and algo == es.ALGO_MERGE
         code = tuner.DTYPE_CODES[dt]
         for m in (lo, n, hi - 1):
             info = es.plan(es.OP_SORT, code, m)
-            radix = es.plan(es.OP_SORT, code, m, 0, es.default_params(algo=es.ALGO_RADIX))
             if m < es.default_params().fallback_threshold and m <= info["small_capacity"]:
                 assert info["path_name"] == "small", (dt, m)  # Algorithm 6 takes the small branch first
                 continue
-            if algo == 3:
-                assert info["path_name"] == "merge", (dt, m)
-            else:
-                assert info["path_name"] == "radix", (dt, m)
-                assert (info["block_threads"], info["items_per_thread"]) == (th, it), (dt, m)
-                assert (radix["block_threads"], radix["items_per_thread"]) != (th, it)
-            assert radix["path_name"] == "radix"
-            pairs = es.plan(es.OP_SORT_PAIRS, code, m, 4)
-            pairs_radix = es.plan(es.OP_SORT_PAIRS, code, m, 4, es.default_params(algo=es.ALGO_RADIX))
-            assert pairs["path_name"] == "radix"
-            assert (pairs["block_threads"], pairs["items_per_thread"]) == (pairs_radix["block_threads"],
-                                                                           pairs_radix["items_per_thread"])
+            assert info["path_name"] == "merge", (dt, m)
+            assert es.plan(es.OP_SORT, code, m, 0, es.default_params(algo=es.ALGO_RADIX))["path_name"] == "radix"
+            assert es.plan(es.OP_SORT_PAIRS, code, m, 4)["path_name"] == "radix"
+            assert es.plan(es.OP_ARGSORT, code, m, 4)["path_name"] == "radix"
             given = es.plan(es.OP_SORT, code, m, 0, es.default_params(block_threads=512, items_per_thread=16))
-            assert (given["block_threads"], given["items_per_thread"]) == (512, 16)
-            assert given["path_name"] == "radix"
+            assert (given["path_name"], given["block_threads"], given["items_per_thread"]) == ("radix", 512, 16)
         for m in (lo - 1, hi):
             if any(r[0] == dt and r[2] <= m < r[3] for r in rows):
                 continue
-            out = es.plan(es.OP_SORT, code, m)
-            dflt = es.plan(es.OP_SORT, code, m, 0, es.default_params(algo=es.ALGO_RADIX))
-            if out["path_name"] == "radix":
-                assert (out["block_threads"], out["items_per_thread"]) == (dflt["block_threads"],
-                                                                       dflt["items_per_thread"]), (dt, m)
-            else:
-                assert out["path_name"] in ("small", "copy"), (dt, m)
+            assert es.plan(es.OP_SORT, code, m)["path_name"] in ("radix", "small", "copy"), (dt, m)
 
 
 def test_auto_table_row_ranges_tile_the_size_classes():
     """A row's range runs from the geometric mean with the next smaller tuned size class of its key type to the
-    one with the next larger (half a decade past the ends); mergesort picks carry no tile."""
+    one with the next larger (half a decade past the ends); only mergesort picks that pass the gain bar, agreed
+    on by every entry of their class, give rows."""
     from paper_2505_18681_amd import tuner
 
     def entry(dtype, n, algo, shape, ms, default_ms):
@@ -281,28 +265,26 @@ def test_auto_table_row_ranges_tile_the_size_classes():
     table = {"entries": [
         entry("int64", 10_000, 4, (0, 0), 1.0, 1.0),
         entry("int64", 20_000, 3, (512, 8), 0.8, 1.0),          # the mergesort: its shape gene is moot
-        entry("float64", 20_000, 4, (1024, 16), 0.8, 1.0),
+        entry("float64", 20_000, 3, (1024, 16), 0.8, 1.0),      # the only float64 class
         entry("int64", 50_000, 3, (0, 0), 0.8, 1.0),
         entry("int64", 50_000, 4, (0, 0), 1.0, 1.0),            # a second run of the class disagrees
-        entry("int64", 100_000, 4, (512, 16), 0.9, 1.0),
-        entry("int32", 100_000, 4, (512, 16), 0.99, 1.0),       # gain below the 2 % bar
-        entry("int32", 1_000_000, 4, (1024, 8), 0.9, 1.0),
-        entry("int32", 1_000_000, 4, (1024, 8), 0.9, 1.0) | {"dist": "zipf"},
+        entry("int64", 100_000, 4, (512, 16), 0.9, 1.0),        # a radix tile pick: no row
+        entry("int64", 200_000, 3, (0, 0), 0.99, 1.0),          # gain below the 2 % bar
+        entry("int32", 1_000_000, 3, (0, 0), 0.9, 1.0),
         entry("int32", 1_000_000, 4, (0, 0), 0.9, 1.0) | {"dist": "zipf"},
     ]}
     rows = tuner.auto_table_rows(table)
-    assert rows == [("int32", 1_000_000, 316_228, 3_162_278, 4, 1024, 8),
-                    ("int64", 20_000, 14_143, 31_623, 3, 0, 0),
-                    ("int64", 100_000, 70_711, 316_228, 4, 512, 16),
-                    ("float64", 20_000, 6_325, 63_246, 4, 1024, 16)]
+    assert rows == [("int32", 1_000_000, 316_228, 3_162_278, 3),
+                    ("int64", 20_000, 14_143, 31_623, 3),
+                    ("float64", 20_000, 6_325, 63_246, 3)]
     # each bound is the smallest length at or above the geometric mean
     assert 14_142 ** 2 < 10_000 * 20_000 <= 14_143 ** 2
-    assert 70_710 ** 2 < 50_000 * 100_000 <= 70_711 ** 2
+    assert 31_622 ** 2 < 20_000 * 50_000 <= 31_623 ** 2
     assert 10 * 316_227 ** 2 < 10 ** 12 <= 10 * 316_228 ** 2
     assert 10 * 6_324 ** 2 < 20_000 ** 2 <= 10 * 6_325 ** 2
     header = tuner.emit_header(table)
-    assert "    {2, 20000, 14143, 31623, 3, 0, 0},  // int64" in header
-    assert "constexpr int kTunedRowCount = 4;" in header
+    assert "    {2, 20000, 14143, 31623, 3},  // int64" in header
+    assert "constexpr int kTunedRowCount = 3;" in header
 
 
 def test_retime_pair_alternates_and_takes_medians():
