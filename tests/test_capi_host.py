@@ -281,3 +281,28 @@ def test_server_config_defaults_and_validation():
     assert es._lib.evosort_server_submit(None, es.INT32, None, 0, None) == es.ERR_INVALID_ARG
     assert es.status_string(es.ERR_OVER_BUDGET).startswith("request")
     assert es.status_string(es.ERR_PENDING).startswith("request")
+
+
+@pytest.mark.parametrize("n, shape", [
+    (2_097_152, (512, 16)),     # 2^21: the mid-size tile
+    (2_097_153, (768, 16)),     # 171 tiles of 12288 keys: every tile on its own CU
+    (2_462_681, (768, 16)),
+    (3_427_305, (768, 20)),     # 224 tiles of 15360
+    (4_043_198, (1024, 16)),    # 247 tiles of 16384
+    (4_769_769, (1024, 20)),    # 233 tiles of 20480; 768 x 24 would put 2 tiles on 3 CUs
+    (5_626_906, (768, 16)),     # 458 tiles: 2 per CU, 24576 keys on the busiest
+    (8_388_608, (1024, 16)),    # 2^23: 512 tiles, 2 per CU
+    (8_388_609, (768, 24)),     # above 2^23: the large-array tile
+])
+def test_default_tile_follows_the_cu_count(n, shape):
+    """Keys-only 4-byte sorts between 2^21 and 2^23 keys take the tile that puts the fewest keys on the busiest
+    of the 256 CUs (hand-computed); pairs, 8-byte keys and other sizes keep their fixed tiles."""
+    p = es.default_params(algo=es.ALGO_RADIX)
+    info = es.plan(es.OP_SORT, es.INT32, n, 0, p)
+    assert (info["block_threads"], info["items_per_thread"]) == shape
+    assert (es.plan(es.OP_SORT, es.FLOAT32, n, 0, p)["block_threads"],
+            es.plan(es.OP_SORT, es.FLOAT32, n, 0, p)["items_per_thread"]) == shape
+    pairs = es.plan(es.OP_SORT_PAIRS, es.INT32, n, 4, p)
+    assert (pairs["block_threads"], pairs["items_per_thread"]) == ((512, 16) if n <= 1 << 21 else (768, 24))
+    wide = es.plan(es.OP_SORT, es.INT64, n, 0, p)
+    assert (wide["block_threads"], wide["items_per_thread"]) == (768, 12)

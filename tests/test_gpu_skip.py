@@ -103,7 +103,7 @@ def test_skip_patterns_with_tile_prefix_route(name):
     import torch
 
     es = require_gpu()
-    n = 5_000_001
+    n = 9_000_001
     keys = _pattern(name, n, 4)
     p = es.default_params()
     assert es.plan(es.OP_SORT, es.INT32, n, 0, p)["tiles"] >= 256
