@@ -202,18 +202,21 @@ RadixShape radix_default_shape_for(int key_bytes, int val_bytes, int bits, int64
     // (by 0.5 to 9 %), where 4-byte keys still gain from 512 x 16
     if (bits == 8 && n <= (int64_t)1 << 21 && !(key_bytes == 8 && val_bytes == 0))
         return RadixShape{512, 16};
-    if (bits == 8 && key_bytes == 4 && val_bytes == 0 && n <= (int64_t)1 << 23) {
-        // Up to a few tiles per CU, a pass lasts about as long as its busiest
-        // CU takes to stream its tiles: ceil(tiles / CUs) tiles of T keys.
-        // Take the shape that puts the fewest keys on the busiest CU (the
-        // larger tile on ties).  At 2.5e6 to 8e6 keys this picked the fastest
-        // of five shapes at 7 of 8 sizes swept, 4.6 % faster than 768 x 24
-        // on average; above 2^23 keys 1024-thread tiles lose more per key
-        // than the rounding gains.
-        constexpr RadixShape kShapes[] = {{768, 24}, {1024, 20}, {1024, 16}, {768, 20}, {768, 16}};
+    if (bits == 8 && key_bytes == 4 && val_bytes == 0 && n <= (int64_t)1 << 26) {
+        // Up to some tens of tiles per CU, a pass lasts about as long as its
+        // busiest CU takes to stream its tiles: ceil(tiles / CUs) tiles of T
+        // keys.  Take the shape that puts the fewest keys on the busiest CU
+        // (the larger tile on ties).  At 2.5e6 to 8e6 keys this picked the
+        // fastest of five shapes at 7 of 8 sizes swept (4.6 % faster than
+        // 768 x 24 on average); above 2^23 keys the 1024 x 20 and smaller
+        // tiles lose more per key than the rounding gains, and the choice is
+        // between 768 x 24 and 1024 x 16 only (1 to 4 % where it switches).
+        constexpr RadixShape kShapes[] = {{768, 24}, {1024, 16}, {1024, 20}, {768, 20}, {768, 16}};
+        const int count = n <= (int64_t)1 << 23 ? 5 : 2;
         RadixShape best = kShapes[0];
         int64_t best_keys = -1, best_tile = 0;
-        for (const RadixShape& c : kShapes) {
+        for (int k = 0; k < count; ++k) {
+            const RadixShape& c = kShapes[k];
             const int64_t tile = (int64_t)c.threads * c.items;
             const int64_t per_cu = ((n + tile - 1) / tile + kComputeUnits - 1) / kComputeUnits * tile;
             if (best_keys < 0 || per_cu < best_keys || (per_cu == best_keys && tile > best_tile)) {

@@ -292,10 +292,14 @@ def test_server_config_defaults_and_validation():
     (4_769_769, (1024, 20)),    # 233 tiles of 20480; 768 x 24 would put 2 tiles on 3 CUs
     (5_626_906, (768, 16)),     # 458 tiles: 2 per CU, 24576 keys on the busiest
     (8_388_608, (1024, 16)),    # 2^23: 512 tiles, 2 per CU
-    (8_388_609, (768, 24)),     # above 2^23: the large-array tile
+    (8_388_609, (768, 24)),     # above 2^23 only 768 x 24 and 1024 x 16 compete: 456 tiles against 513
+    (10_000_000, (1024, 16)),   # 611 tiles, 3 per CU: 49152 keys on the busiest against 55296
+    (12_647_247, (768, 24)),    # 687 tiles against 772
+    (67_108_864, (1024, 16)),   # 2^26: 4096 tiles, 16 per CU
+    (67_108_865, (768, 24)),    # above 2^26: the large-array tile
 ])
 def test_default_tile_follows_the_cu_count(n, shape):
-    """Keys-only 4-byte sorts between 2^21 and 2^23 keys take the tile that puts the fewest keys on the busiest
+    """Keys-only 4-byte sorts between 2^21 and 2^26 keys take the tile that puts the fewest keys on the busiest
     of the 256 CUs (hand-computed); pairs, 8-byte keys and other sizes keep their fixed tiles."""
     p = es.default_params(algo=es.ALGO_RADIX)
     info = es.plan(es.OP_SORT, es.INT32, n, 0, p)
