@@ -567,7 +567,7 @@ def fit_tile_formula(es, table: dict, key_bytes: int) -> Tuple[float, float, flo
 
 # Coefficients of that fit on the packaged table (tests refit them from the
 # table): log2(keys per tile) = a x^2 + b x + c, x = log10(n).
-GPU_TILE_FORMULA = {4: (-0.0989, 1.9419, 5.0076), 8: (-0.3014, 4.4195, -2.9973)}
+GPU_TILE_FORMULA = {4: (-0.0852, 1.8031, 5.3049), 8: (-0.3618, 5.2535, -5.7880)}
 
 # Largest tile the radix pass compiles for keys only at 8-bit digits.
 _MAX_TILE = {4: 768 * 24, 8: 768 * 12}
@@ -591,10 +591,12 @@ def closed_form_params(es, dtype_name: str, n: int):
     return to_params(es, {"algo": 4, "digit_bits": 8, "shape": best})
 
 
-# A table entry overrides the hand-coded default tile only where the GA's
-# re-timed pick beat the re-timed default by this much (smaller gains are
-# within the timing noise of one tuning run).
-AUTO_MIN_GAIN = 0.02
+# A table entry becomes a row of the compiled table only where the GA's
+# re-timed pick beat the re-timed default by this much: smaller gains moved
+# between tuning runs by as much as their size (the mergesort for float64 at
+# 1e5 keys: 4.5, 2.6, 1.1 and 2.0 % in four runs) and were losses at the ends
+# of the row's range (10 % at 1.41e5 keys).
+AUTO_MIN_GAIN = 0.05
 
 
 def _cut(num: int, den: int = 1) -> int:
