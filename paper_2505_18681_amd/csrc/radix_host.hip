@@ -202,7 +202,7 @@ RadixShape radix_default_shape_for(int key_bytes, int val_bytes, int bits, int64
     // (by 0.5 to 9 %), where 4-byte keys still gain from 512 x 16
     if (bits == 8 && n <= (int64_t)1 << 21 && !(key_bytes == 8 && val_bytes == 0))
         return RadixShape{512, 16};
-    if (bits == 8 && key_bytes == 4 && val_bytes == 0 && n <= (int64_t)1 << 26) {
+    if (bits == 8 && key_bytes == 4 && val_bytes != 8 && n <= (int64_t)1 << 26) {
         // Up to some tens of tiles per CU, a pass lasts about as long as its
         // busiest CU takes to stream its tiles: ceil(tiles / CUs) tiles of T
         // keys.  Take the shape that puts the fewest keys on the busiest CU
@@ -211,12 +211,18 @@ RadixShape radix_default_shape_for(int key_bytes, int val_bytes, int bits, int64
         // 768 x 24 on average); above 2^23 keys the 1024 x 20 and smaller
         // tiles lose more per key than the rounding gains, and the choice is
         // between 768 x 24 and 1024 x 16 only (1 to 4 % where it switches).
+        // Pairs with 4-byte values (and argsort with 32-bit indices) take the
+        // same rule over the shapes compiled for them (3.3 % faster on
+        // average over 24 sizes from 2.2e6 to 6.6e7 keys, at most 0.4 %
+        // slower).
         constexpr RadixShape kShapes[] = {{768, 24}, {1024, 16}, {1024, 20}, {768, 20}, {768, 16}};
         const int count = n <= (int64_t)1 << 23 ? 5 : 2;
         RadixShape best = kShapes[0];
         int64_t best_keys = -1, best_tile = 0;
         for (int k = 0; k < count; ++k) {
             const RadixShape& c = kShapes[k];
+            if (!radix_pass_available(key_bytes, val_bytes, bits, c, 4))
+                continue;
             const int64_t tile = (int64_t)c.threads * c.items;
             const int64_t per_cu = ((n + tile - 1) / tile + kComputeUnits - 1) / kComputeUnits * tile;
             if (best_keys < 0 || per_cu < best_keys || (per_cu == best_keys && tile > best_tile)) {

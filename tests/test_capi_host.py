@@ -283,30 +283,34 @@ def test_server_config_defaults_and_validation():
     assert es.status_string(es.ERR_PENDING).startswith("request")
 
 
-@pytest.mark.parametrize("n, shape", [
-    (2_097_152, (512, 16)),     # 2^21: the mid-size tile
-    (2_097_153, (768, 16)),     # 171 tiles of 12288 keys: every tile on its own CU
-    (2_462_681, (768, 16)),
-    (3_427_305, (768, 20)),     # 224 tiles of 15360
-    (4_043_198, (1024, 16)),    # 247 tiles of 16384
-    (4_769_769, (1024, 20)),    # 233 tiles of 20480; 768 x 24 would put 2 tiles on 3 CUs
-    (5_626_906, (768, 16)),     # 458 tiles: 2 per CU, 24576 keys on the busiest
-    (8_388_608, (1024, 16)),    # 2^23: 512 tiles, 2 per CU
-    (8_388_609, (768, 24)),     # above 2^23 only 768 x 24 and 1024 x 16 compete: 456 tiles against 513
-    (10_000_000, (1024, 16)),   # 611 tiles, 3 per CU: 49152 keys on the busiest against 55296
-    (12_647_247, (768, 24)),    # 687 tiles against 772
-    (67_108_864, (1024, 16)),   # 2^26: 4096 tiles, 16 per CU
-    (67_108_865, (768, 24)),    # above 2^26: the large-array tile
+@pytest.mark.parametrize("n, shape, pair_shape", [
+    (2_097_152, (512, 16), (512, 16)),      # 2^21: the mid-size tile
+    (2_097_153, (768, 16), (768, 16)),      # 171 tiles of 12288 keys: every tile on its own CU
+    (2_462_681, (768, 16), (768, 16)),
+    (3_427_305, (768, 20), (768, 20)),      # 224 tiles of 15360
+    (4_043_198, (1024, 16), (1024, 16)),    # 247 tiles of 16384
+    (4_769_769, (1024, 20), (768, 16)),     # 233 tiles of 20480 (not compiled with values: 389 of 12288)
+    (5_626_906, (768, 16), (768, 16)),      # 458 tiles: 2 per CU, 24576 keys on the busiest
+    (8_388_608, (1024, 16), (1024, 16)),    # 2^23: 512 tiles, 2 per CU
+    (8_388_609, (768, 24), (768, 24)),      # above 2^23 only 768 x 24 and 1024 x 16 compete: 456 tiles against 513
+    (10_000_000, (1024, 16), (1024, 16)),   # 611 tiles, 3 per CU: 49152 keys on the busiest against 55296
+    (12_647_247, (768, 24), (768, 24)),     # 687 tiles against 772
+    (67_108_864, (1024, 16), (1024, 16)),   # 2^26: 4096 tiles, 16 per CU
+    (67_108_865, (768, 24), (768, 24)),     # above 2^26: the large-array tile
 ])
-def test_default_tile_follows_the_cu_count(n, shape):
-    """Keys-only 4-byte sorts between 2^21 and 2^26 keys take the tile that puts the fewest keys on the busiest
-    of the 256 CUs (hand-computed); pairs, 8-byte keys and other sizes keep their fixed tiles."""
+def test_default_tile_follows_the_cu_count(n, shape, pair_shape):
+    """4-byte keys between 2^21 and 2^26 keys, alone or with 4-byte values (or 32-bit argsort indices), take the
+    tile that puts the fewest keys on the busiest of the 256 CUs among the shapes compiled for them
+    (hand-computed); 8-byte values and 8-byte keys keep their fixed tiles."""
     p = es.default_params(algo=es.ALGO_RADIX)
-    info = es.plan(es.OP_SORT, es.INT32, n, 0, p)
-    assert (info["block_threads"], info["items_per_thread"]) == shape
-    assert (es.plan(es.OP_SORT, es.FLOAT32, n, 0, p)["block_threads"],
-            es.plan(es.OP_SORT, es.FLOAT32, n, 0, p)["items_per_thread"]) == shape
-    pairs = es.plan(es.OP_SORT_PAIRS, es.INT32, n, 4, p)
-    assert (pairs["block_threads"], pairs["items_per_thread"]) == ((512, 16) if n <= 1 << 21 else (768, 24))
-    wide = es.plan(es.OP_SORT, es.INT64, n, 0, p)
-    assert (wide["block_threads"], wide["items_per_thread"]) == (768, 12)
+
+    def tile(op, code, vb):
+        info = es.plan(op, code, n, vb, p)
+        return info["block_threads"], info["items_per_thread"]
+
+    assert tile(es.OP_SORT, es.INT32, 0) == shape
+    assert tile(es.OP_SORT, es.FLOAT32, 0) == shape
+    assert tile(es.OP_SORT_PAIRS, es.INT32, 4) == pair_shape
+    assert tile(es.OP_ARGSORT, es.UINT32, 4) == pair_shape
+    assert tile(es.OP_SORT_PAIRS, es.INT32, 8) == ((512, 16) if n <= 1 << 21 else (512, 24))
+    assert tile(es.OP_SORT, es.INT64, 0) == (768, 12)

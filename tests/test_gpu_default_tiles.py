@@ -87,3 +87,29 @@ def test_default_tiles_descending_and_in_place(wide):
     k = to_dev(keys)
     es.sort(k, params=p, out=k, check=True)
     assert_bits_equal(to_np(k), oracle.sort(keys, descending=True), "descending in place")
+
+
+@pytest.mark.parametrize("dt, n", [(np.int32, 2_462_681), (np.int32, 3_427_305), (np.uint32, 4_043_198),
+                                   (np.float32, 4_769_769), (np.int32, 10_000_007)])
+def test_cu_rounded_tiles_match_oracle(dt, n):
+    """The tiles the CU-rounding rule picks between 2^21 and 2^26 keys (768 x 16, 768 x 20, 1024 x 16,
+    1024 x 20): keys only, pairs with 4-byte values and argsort with 32-bit indices, element by element
+    against the oracle, ties included."""
+    import torch
+
+    es = require_gpu()
+    keys = workloads.float_mix(dt, n, 17) if np.dtype(dt).kind == "f" else workloads.uniform(dt, n, 17)
+    keys[::7] = keys[3]
+    perm = oracle.stable_perm(keys)
+    k = to_dev(keys)
+    p = es.default_params(algo=es.ALGO_RADIX)
+    code = es.dtype_code(k.dtype)
+    shapes = {(es.plan(op, code, n, vb, p)["block_threads"], es.plan(op, code, n, vb, p)["items_per_thread"])
+              for op, vb in ((es.OP_SORT, 0), (es.OP_SORT_PAIRS, 4))}
+    assert shapes & {(768, 16), (768, 20), (1024, 16), (1024, 20)}, shapes
+    assert_bits_equal(to_np(es.sort(k, params=p, check=True)), keys[perm], "keys")
+    v = (np.arange(n, dtype=np.int64) * 5 + 1).astype(np.int32)
+    ko, vo = es.sort_pairs(k, to_dev(v), params=p, check=True)
+    assert_bits_equal(to_np(ko), keys[perm], "pairs keys")
+    assert_bits_equal(to_np(vo), v[perm], "pairs values")
+    assert np.array_equal(to_np(es.argsort(k, index_dtype=torch.int32, params=p, check=True)), perm), "argsort"
