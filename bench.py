@@ -538,7 +538,7 @@ def run_paper_sweep(es, torch, n: int, seed: int, steps: int = 5):
             "entries": out}
 
 
-def run_routines_bench(es, torch, seed: int, n_merge: int = 100_000_000, steps: int = 5):
+def run_routines_bench(es, torch, seed: int, n_merge: int = 100_000_000, steps: int = 10):
     """The other two routines of the adaptive partition sort, on uniform int32 keys with default parameters:
     the mergesort at n_merge keys (block sort, then merge-path rounds; roofline of each kernel from its
     algorithmic bytes, one read and one write of every key per launch) and the one-workgroup sort at its
@@ -550,8 +550,12 @@ def run_routines_bench(es, torch, seed: int, n_merge: int = 100_000_000, steps: 
     stream = torch.cuda.current_stream()
 
     def timed(fn, k):
+        t_warm = time.perf_counter()
         fn()
         torch.cuda.synchronize()
+        while time.perf_counter() - t_warm < 0.25:  # untimed calls until the clocks are up
+            fn()
+            torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
         for _ in range(k):
