@@ -301,7 +301,7 @@ def test_server_config_defaults_and_validation():
 def test_default_tile_follows_the_cu_count(n, shape, pair_shape):
     """4-byte keys between 2^21 and 2^26 keys, alone or with 4-byte values (or 32-bit argsort indices), take the
     tile that puts the fewest keys on the busiest of the 256 CUs among the shapes compiled for them
-    (hand-computed); 8-byte values and 8-byte keys keep their fixed tiles."""
+    (hand-computed); pairs with an 8-byte word take fixed mid-size tiles there, 8-byte keys alone keep theirs."""
     p = es.default_params(algo=es.ALGO_RADIX)
 
     def tile(op, code, vb):
@@ -312,5 +312,10 @@ def test_default_tile_follows_the_cu_count(n, shape, pair_shape):
     assert tile(es.OP_SORT, es.FLOAT32, 0) == shape
     assert tile(es.OP_SORT_PAIRS, es.INT32, 4) == pair_shape
     assert tile(es.OP_ARGSORT, es.UINT32, 4) == pair_shape
-    assert tile(es.OP_SORT_PAIRS, es.INT32, 8) == ((512, 16) if n <= 1 << 21 else (512, 24))
+    # an 8-byte word among key and value: fixed mid-size tiles between 2^21 and 2^26 keys
+    mid = 1 << 21 < n <= 1 << 26
+    assert tile(es.OP_SORT_PAIRS, es.INT32, 8) == ((768, 16) if mid else (512, 16) if n <= 1 << 21 else (512, 24))
+    assert tile(es.OP_ARGSORT, es.INT32, 8) == tile(es.OP_SORT_PAIRS, es.INT32, 8)
+    assert tile(es.OP_SORT_PAIRS, es.INT64, 4) == ((768, 16) if mid else (512, 16) if n <= 1 << 21 else (512, 24))
+    assert tile(es.OP_SORT_PAIRS, es.INT64, 8) == ((768, 12) if mid else (512, 16))
     assert tile(es.OP_SORT, es.INT64, 0) == (768, 12)

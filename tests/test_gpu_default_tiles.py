@@ -21,8 +21,12 @@ from gpu_util import assert_bits_equal, require_gpu, to_dev, to_np
 pytestmark = pytest.mark.gpu
 
 N = (1 << 22) + 12345
-EXPECTED_TILE = {(4, 0): (768, 24), (4, 4): (768, 24), (4, 8): (512, 24),
-                 (8, 0): (768, 12), (8, 4): (512, 24), (8, 8): (512, 16)}
+# the default at N keys (pairs with an 8-byte word take their mid-size tiles below 2^26 keys), and the
+# large-array tiles those pairs take above 2^26 keys, checked here at N by asking for them
+EXPECTED_TILE = {(4, 0): (768, 24), (4, 4): (768, 24), (4, 8): (768, 16),
+                 (8, 0): (768, 12), (8, 4): (768, 16), (8, 8): (768, 12)}
+LARGE_TILE = {(4, 0): (768, 24), (4, 4): (768, 24), (4, 8): (512, 24),
+              (8, 0): (768, 12), (8, 4): (512, 24), (8, 8): (512, 16)}
 _CACHE = {}
 
 
@@ -41,40 +45,59 @@ def _case(dt):
     return _CACHE[dt]
 
 
+@pytest.mark.parametrize("tiles", ["default", "large"])
 @pytest.mark.parametrize("wide", [False, True], ids=["status32", "status64"])
 @pytest.mark.parametrize("dt", [np.int32, np.float32, np.uint32, np.int64, np.float64])
-def test_default_large_array_tiles(dt, wide):
+def test_default_large_array_tiles(dt, wide, tiles):
+    """Keys only, pairs with 4- and 8-byte values and argsort with 32- and 64-bit indices on the default tiles
+    at N keys, and on the large-array tiles where those differ, element by element against the oracle."""
     import torch
 
     es = require_gpu()
     keys, perm = _case(dt)
     kb = np.dtype(dt).itemsize
     code = es.dtype_code(torch.from_numpy(keys[:1]).dtype)
-    # A_code 4: the hand-coded tiles (the automatic choice may take the tuner's tile at some sizes; those
-    # kernels are checked with the tuner's tests)
-    p = es.default_params(algo=es.ALGO_RADIX, debug_flags=es.DEBUG_WIDE_STATUS if wide else 0)
+    flags = es.DEBUG_WIDE_STATUS if wide else 0
+    table = EXPECTED_TILE if tiles == "default" else LARGE_TILE
+
+    # A_code 4: the hand-coded tiles (the automatic choice may take the tuner's routine at some sizes; those
+    # sorts are checked with the tuner's tests)
+    def params(vb):
+        if tiles == "default":
+            return es.default_params(algo=es.ALGO_RADIX, debug_flags=flags)
+        t, i = LARGE_TILE[(kb, vb)]
+        return es.default_params(algo=es.ALGO_RADIX, debug_flags=flags, block_threads=t, items_per_thread=i)
+
+    def runs(vb):  # the large-array pass checks only the tiles the default does not already take
+        return tiles == "default" or LARGE_TILE[(kb, vb)] != EXPECTED_TILE[(kb, vb)]
+
     for op, vb in ((es.OP_SORT, 0), (es.OP_SORT_PAIRS, 4), (es.OP_SORT_PAIRS, 8), (es.OP_ARGSORT, 4),
                    (es.OP_ARGSORT, 8)):
-        info = es.plan(op, code, N, vb, p)
+        info = es.plan(op, code, N, vb, params(vb))
         assert info["path_name"] == "radix"
-        assert (info["block_threads"], info["items_per_thread"]) == EXPECTED_TILE[(kb, vb)], (op, vb, info)
+        assert (info["block_threads"], info["items_per_thread"]) == table[(kb, vb)], (op, vb, info)
         assert info["status_bytes"] == (8 if wide else 4)
         assert info["tiles"] > 200
+    if not any(runs(vb) for vb in (0, 4, 8)):
+        return
     want = keys[perm]
     k = to_dev(keys)
-    assert_bits_equal(to_np(es.sort(k, params=p, check=True)), want, "keys")
-    v4 = (np.arange(N, dtype=np.int64) * 7 + 3).astype(np.int32)
-    k4, o4 = es.sort_pairs(k, to_dev(v4), params=p, check=True)
-    assert_bits_equal(to_np(k4), want, "pairs(4) keys")
-    assert_bits_equal(to_np(o4), v4[perm], "pairs(4) values")
-    v8 = (np.arange(N, dtype=np.int64) * 2654435761) % (2 ** 61)
-    k8, o8 = es.sort_pairs(k, to_dev(v8), params=p, check=True)
-    assert_bits_equal(to_np(k8), want, "pairs(8) keys")
-    assert_bits_equal(to_np(o8), v8[perm], "pairs(8) values")
-    assert np.array_equal(to_np(es.argsort(k, index_dtype=torch.int32, params=p, check=True)),
-                          perm.astype(np.int32)), "argsort int32"
-    assert np.array_equal(to_np(es.argsort(k, index_dtype=torch.int64, params=p, check=True)), perm), \
-        "argsort int64"
+    if runs(0):
+        assert_bits_equal(to_np(es.sort(k, params=params(0), check=True)), want, "keys")
+    if runs(4):
+        v4 = (np.arange(N, dtype=np.int64) * 7 + 3).astype(np.int32)
+        k4, o4 = es.sort_pairs(k, to_dev(v4), params=params(4), check=True)
+        assert_bits_equal(to_np(k4), want, "pairs(4) keys")
+        assert_bits_equal(to_np(o4), v4[perm], "pairs(4) values")
+        assert np.array_equal(to_np(es.argsort(k, index_dtype=torch.int32, params=params(4), check=True)),
+                              perm.astype(np.int32)), "argsort int32"
+    if runs(8):
+        v8 = (np.arange(N, dtype=np.int64) * 2654435761) % (2 ** 61)
+        k8, o8 = es.sort_pairs(k, to_dev(v8), params=params(8), check=True)
+        assert_bits_equal(to_np(k8), want, "pairs(8) keys")
+        assert_bits_equal(to_np(o8), v8[perm], "pairs(8) values")
+        assert np.array_equal(to_np(es.argsort(k, index_dtype=torch.int64, params=params(8), check=True)),
+                              perm), "argsort int64"
 
 
 @pytest.mark.parametrize("wide", [False, True], ids=["status32", "status64"])
@@ -130,3 +153,29 @@ def test_mid_size_8_byte_keys_take_the_large_tile(dt, n):
     pairs = es.plan(es.OP_SORT_PAIRS, code, n, 8, p)
     assert (pairs["block_threads"], pairs["items_per_thread"]) == (512, 16)
     assert_bits_equal(to_np(es.sort(k, params=p, check=True)), oracle.sort(keys), "keys")
+
+
+@pytest.mark.parametrize("kdt, vb, shape", [(np.int32, 8, (768, 16)), (np.float64, 4, (768, 16)),
+                                            (np.int64, 8, (768, 12))])
+def test_mid_size_pairs_with_an_8_byte_word(kdt, vb, shape):
+    """Pairs with an 8-byte key or value between 2^21 and 2^26 keys sort on their mid-size tile (768 x 16 with
+    one 8-byte word, 768 x 12 with two), and argsort with 64-bit indices likewise, element by element against
+    the oracle."""
+    import torch
+
+    es = require_gpu()
+    n = 3_000_017
+    keys = workloads.float_mix(kdt, n, 29) if np.dtype(kdt).kind == "f" else workloads.uniform(kdt, n, 29)
+    keys[::6] = keys[1]
+    perm = oracle.stable_perm(keys)
+    k = to_dev(keys)
+    p = es.default_params(algo=es.ALGO_RADIX)
+    code = es.dtype_code(k.dtype)
+    info = es.plan(es.OP_SORT_PAIRS, code, n, vb, p)
+    assert (info["block_threads"], info["items_per_thread"]) == shape
+    v = (np.arange(n, dtype=np.int64) * 3 + 7)
+    v = v.astype(np.int32) if vb == 4 else v
+    ko, vo = es.sort_pairs(k, to_dev(v), params=p, check=True)
+    assert_bits_equal(to_np(ko), keys[perm], "pairs keys")
+    assert_bits_equal(to_np(vo), v[perm], "pairs values")
+    assert np.array_equal(to_np(es.argsort(k, index_dtype=torch.int64, params=p, check=True)), perm), "argsort"
