@@ -197,11 +197,11 @@ RadixShape radix_default_shape_for(int key_bytes, int val_bytes, int bits, int64
 {
     if (bits == 8 && n <= (int64_t)1 << 19)
         return RadixShape{512, 8};
-    // 8-byte keys without values take their large-array tile from 2^19 keys
-    // on: 768 x 12 beat 512 x 16 at every size swept between 6e5 and 2e6 keys
-    // (by 0.5 to 9 %), where 4-byte keys still gain from 512 x 16
-    if (bits == 8 && n <= (int64_t)1 << 21 && !(key_bytes == 8 && val_bytes == 0))
-        return RadixShape{512, 16};
+    // From 2^19 to 2^21 keys 768 x 12 for every key and value width: it beat
+    // 512 x 16 at every size swept there, keys only and pairs (2 to 3.5 % on
+    // average, up to 9 %)
+    if (bits == 8 && n <= (int64_t)1 << 21)
+        return RadixShape{768, 12};
     // Pairs with an 8-byte word among key and value, between 2^21 and 2^26
     // keys: 768 x 16 (one 8-byte word) and 768 x 12 (8-byte keys and values)
     // beat the large-array tiles 512 x 24 and 512 x 16 at every size swept

@@ -284,7 +284,7 @@ def test_server_config_defaults_and_validation():
 
 
 @pytest.mark.parametrize("n, shape, pair_shape", [
-    (2_097_152, (512, 16), (512, 16)),      # 2^21: the mid-size tile
+    (2_097_152, (768, 12), (768, 12)),      # 2^21: the mid-size tile of every width
     (2_097_153, (768, 16), (768, 16)),      # 171 tiles of 12288 keys: every tile on its own CU
     (2_462_681, (768, 16), (768, 16)),
     (3_427_305, (768, 20), (768, 20)),      # 224 tiles of 15360
@@ -314,8 +314,9 @@ def test_default_tile_follows_the_cu_count(n, shape, pair_shape):
     assert tile(es.OP_ARGSORT, es.UINT32, 4) == pair_shape
     # an 8-byte word among key and value: fixed mid-size tiles between 2^21 and 2^26 keys
     mid = 1 << 21 < n <= 1 << 26
-    assert tile(es.OP_SORT_PAIRS, es.INT32, 8) == ((768, 16) if mid else (512, 16) if n <= 1 << 21 else (512, 24))
+    small = n <= 1 << 21
+    assert tile(es.OP_SORT_PAIRS, es.INT32, 8) == ((768, 16) if mid else (768, 12) if small else (512, 24))
     assert tile(es.OP_ARGSORT, es.INT32, 8) == tile(es.OP_SORT_PAIRS, es.INT32, 8)
-    assert tile(es.OP_SORT_PAIRS, es.INT64, 4) == ((768, 16) if mid else (512, 16) if n <= 1 << 21 else (512, 24))
-    assert tile(es.OP_SORT_PAIRS, es.INT64, 8) == ((768, 12) if mid else (512, 16))
+    assert tile(es.OP_SORT_PAIRS, es.INT64, 4) == ((768, 16) if mid else (768, 12) if small else (512, 24))
+    assert tile(es.OP_SORT_PAIRS, es.INT64, 8) == ((768, 12) if mid or small else (512, 16))
     assert tile(es.OP_SORT, es.INT64, 0) == (768, 12)

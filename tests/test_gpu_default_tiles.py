@@ -139,9 +139,9 @@ def test_cu_rounded_tiles_match_oracle(dt, n):
 
 
 @pytest.mark.parametrize("dt, n", [(np.int64, 524_289), (np.float64, 1_000_003), (np.int64, 2_097_152)])
-def test_mid_size_8_byte_keys_take_the_large_tile(dt, n):
-    """8-byte keys without values above 2^19 keys sort on the 768 x 12 tile, element by element like the
-    oracle; with values they keep 512 x 16 up to 2^21 keys."""
+def test_mid_size_keys_take_768x12(dt, n):
+    """Keys above 2^19 keys sort on the 768 x 12 tile up to 2^21 keys (and 8-byte keys without values above),
+    element by element like the oracle; pairs with 8-byte values take it too."""
     es = require_gpu()
     keys = workloads.float_mix(dt, n, 23) if np.dtype(dt).kind == "f" else workloads.uniform(dt, n, 23)
     keys[::9] = keys[2]
@@ -151,8 +151,13 @@ def test_mid_size_8_byte_keys_take_the_large_tile(dt, n):
     info = es.plan(es.OP_SORT, code, n, 0, p)
     assert (info["block_threads"], info["items_per_thread"]) == (768, 12)
     pairs = es.plan(es.OP_SORT_PAIRS, code, n, 8, p)
-    assert (pairs["block_threads"], pairs["items_per_thread"]) == (512, 16)
+    assert (pairs["block_threads"], pairs["items_per_thread"]) == (768, 12)
     assert_bits_equal(to_np(es.sort(k, params=p, check=True)), oracle.sort(keys), "keys")
+    v = np.arange(n, dtype=np.int64) * 11 - 3
+    ko, vo = es.sort_pairs(k, to_dev(v), params=p, check=True)
+    perm = oracle.stable_perm(keys)
+    assert_bits_equal(to_np(ko), keys[perm], "pairs keys")
+    assert_bits_equal(to_np(vo), v[perm], "pairs values")
 
 
 @pytest.mark.parametrize("kdt, vb, shape", [(np.int32, 8, (768, 16)), (np.float64, 4, (768, 16)),
