@@ -228,7 +228,7 @@ RadixShape radix_default_shape_for(int key_bytes, int val_bytes, int bits, int64
         int64_t best_keys = -1, best_tile = 0;
         for (int k = 0; k < count; ++k) {
             const RadixShape& c = kShapes[k];
-            if (!radix_pass_available(key_bytes, val_bytes, bits, c, 4))
+            if (!radix_pass_available(key_bytes, val_bytes, bits, c, 4))  // same set at either word width
                 continue;
             const int64_t tile = (int64_t)c.threads * c.items;
             const int64_t per_cu = ((n + tile - 1) / tile + kComputeUnits - 1) / kComputeUnits * tile;
