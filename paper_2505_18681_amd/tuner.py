@@ -567,7 +567,7 @@ def fit_tile_formula(es, table: dict, key_bytes: int) -> Tuple[float, float, flo
 
 # Coefficients of that fit on the packaged table (tests refit them from the
 # table): log2(keys per tile) = a x^2 + b x + c, x = log10(n).
-GPU_TILE_FORMULA = {4: (-0.0852, 1.8031, 5.3049), 8: (-0.3618, 5.2535, -5.7880)}
+GPU_TILE_FORMULA = {4: (-0.0990, 1.9519, 4.9459), 8: (-0.3618, 5.2535, -5.7880)}
 
 # Largest tile the radix pass compiles for keys only at 8-bit digits.
 _MAX_TILE = {4: 768 * 24, 8: 768 * 12}
