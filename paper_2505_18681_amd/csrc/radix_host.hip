@@ -31,12 +31,18 @@ constexpr int kHistThreads = 256;
 int histogram_grid(int64_t n)
 {
     // Enough workgroups to fill 256 CUs several times over; each thread then
-    // walks the keys with a grid stride.
+    // walks the keys with a grid stride.  Up to 2^23 keys at most 384: every
+    // workgroup flushes its counts into the same few global words with
+    // atomics, and beyond about one workgroup per CU those flushes cost more
+    // than the reads they spread (4-byte keys 2.5 to 8 % faster from 1.7e6
+    // to 4.2e6 keys; 8-byte keys unchanged).
     int64_t want = (n + 16 * kHistThreads - 1) / (16 * kHistThreads);
     if (want < 1)
         want = 1;
     if (want > 4096)
         want = 4096;
+    if (n <= (int64_t)1 << 23 && want > 384)
+        want = 384;
     return (int)want;
 }
 }  // namespace
