@@ -25,24 +25,28 @@ hipError_t seg_pass_dispatch_k8_v0(RadixShape, const KeyDesc&, const SegPassArgs
 hipError_t seg_pass_dispatch_k8_v4(RadixShape, const KeyDesc&, const SegPassArgs&, uint32_t, hipStream_t, bool*);
 hipError_t seg_pass_dispatch_k8_v8(RadixShape, const KeyDesc&, const SegPassArgs&, uint32_t, hipStream_t, bool*);
 
+// Compute units of the MI355X (gfx950) the size-dependent grids and tiles are
+// chosen for.
+constexpr int64_t kComputeUnits = 256;
+
 namespace {
 constexpr int kHistThreads = 256;
 
 int histogram_grid(int64_t n)
 {
     // Enough workgroups to fill 256 CUs several times over; each thread then
-    // walks the keys with a grid stride.  Up to 2^23 keys at most 384: every
-    // workgroup flushes its counts into the same few global words with
-    // atomics, and beyond about one workgroup per CU those flushes cost more
-    // than the reads they spread (4-byte keys 2.5 to 8 % faster from 1.7e6
-    // to 4.2e6 keys; 8-byte keys unchanged).
+    // walks the keys with a grid stride.  Up to 2^23 keys at most one per CU:
+    // every workgroup flushes its counts into the same few global words with
+    // atomics, and beyond one workgroup per CU those flushes cost more than
+    // the reads they spread (4-byte keys 2 to 9 % faster from 1.1e6 to 4.6e6
+    // keys; 8-byte keys within 1 %).
     int64_t want = (n + 16 * kHistThreads - 1) / (16 * kHistThreads);
     if (want < 1)
         want = 1;
     if (want > 4096)
         want = 4096;
-    if (n <= (int64_t)1 << 23 && want > 384)
-        want = 384;
+    if (n <= (int64_t)1 << 23 && want > kComputeUnits)
+        want = kComputeUnits;
     return (int)want;
 }
 }  // namespace
@@ -196,9 +200,6 @@ RadixShape radix_default_shape(int key_bytes, int val_bytes, int bits)
 // 0.116, 3e5 0.163 / 0.136 with 512 x 8; 1e6 0.182 / 0.155 with 512 x 16; at
 // 3e6 the default is within 2 %.  1e5 int64 keys: 0.216 / 0.189; 1e5 int32
 // keys with 8-byte values: 0.148 / 0.123.
-// Compute units of the MI355X (gfx950) the size-dependent tiles are chosen for.
-constexpr int64_t kComputeUnits = 256;
-
 RadixShape radix_default_shape_for(int key_bytes, int val_bytes, int bits, int64_t n)
 {
     if (bits == 8 && n <= (int64_t)1 << 19)
